@@ -1,0 +1,224 @@
+"""Seeded synthetic inputs for every workload of the gradient library.
+
+This module only draws random numbers and lays out index structures; it holds
+none of the objective's arithmetic, so both the FP64 oracle and the HIP path
+can take their inputs from it without sharing any of the method.
+
+Every generator uses ``numpy.random.default_rng(seed)`` (PCG64) and draws its
+arrays in a fixed order, so a (workload, seed) pair names one exact input.
+
+Workloads (the paper's own example, section 4, is a 1D stencil on a vector of
+up to 10,000 entries; the element form below generalises it):
+
+* ``chain(n)``          -- 1D chain of n nodes, n-1 two-node elements,
+                           B[e] = (-n, +n), w_e = 1/n, x ~ U(-1, 1)          (seed 0)
+* ``hex_mesh(s)``       -- structured s^3 hex mesh, (s-1)^3 eight-node elements
+                           in lexicographic order, B ~ N(0,1), w ~ U(0.5,1.5),
+                           x ~ U(-1, 1)                                       (seed 1)
+* ``dense(n)``          -- A n x n with entries N(0, 1/n), x ~ U(-1,1),
+                           w ~ U(0.5,1.5)                                     (seed 2)
+* ``batched_dense(m,n)``-- A m x m N(0, 1/m), X m x n ~ U(-1,1),
+                           W m x n ~ U(0.5,1.5)                               (seed 3)
+* ``uneven_batch(k)``   -- k hex meshes with side s = round(10**(1+U)),
+                           U ~ U[0,1), concatenated                           (seed 4)
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+
+SEED_CHAIN = 0
+SEED_HEX = 1
+SEED_DENSE = 2
+SEED_BDENSE = 3
+SEED_BATCH = 4
+
+
+@dataclasses.dataclass
+class Mesh:
+    """Element-connectivity workload: conn[E*k] int32, B[E*k], w[E], x[N]."""
+
+    n_nodes: int
+    n_elems: int
+    k: int
+    conn: np.ndarray  # int32, shape (E, k), row-major
+    B: np.ndarray     # float64, shape (E, k)
+    w: np.ndarray     # float64, shape (E,)
+    x: np.ndarray     # float64, shape (N,)
+    name: str = ""
+
+    def astype(self, dtype) -> "Mesh":
+        """Same mesh with B, w, x rounded to ``dtype`` (conn unchanged)."""
+        return Mesh(self.n_nodes, self.n_elems, self.k, self.conn,
+                    self.B.astype(dtype), self.w.astype(dtype),
+                    self.x.astype(dtype), self.name)
+
+    @property
+    def nbytes_inputs(self) -> int:
+        return self.conn.nbytes + self.B.nbytes + self.w.nbytes + self.x.nbytes
+
+
+def chain_conn(n: int) -> np.ndarray:
+    """Two-node elements (e, e+1) for e < n-1."""
+    e = np.arange(max(n - 1, 0), dtype=np.int64)
+    return np.stack([e, e + 1], axis=1).astype(np.int32)
+
+
+def chain(n: int = 10_000, seed: int = SEED_CHAIN) -> Mesh:
+    """1D chain: n nodes, E = n-1 elements, u_e = n (x_{e+1} - x_e), w_e = 1/n."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1.0, 1.0, n)
+    E = max(n - 1, 0)
+    conn = chain_conn(n)
+    B = np.empty((E, 2), dtype=np.float64)
+    B[:, 0] = -float(n)
+    B[:, 1] = float(n)
+    w = np.full(E, 1.0 / n, dtype=np.float64)
+    return Mesh(n, E, 2, conn, B, w, x, f"chain{n}")
+
+
+def hex_conn(s: int) -> np.ndarray:
+    """Lexicographic connectivity of an s^3-node structured hex mesh.
+
+    node(i, j, k) = i + s*(j + s*k), i fastest; element (i, j, k) with
+    i, j, k < s-1 is numbered i + (s-1)*(j + (s-1)*k); its corner
+    c = di + 2*dj + 4*dk is node(i+di, j+dj, k+dk).
+    """
+    m = s - 1
+    if m <= 0:
+        return np.zeros((0, 8), dtype=np.int32)
+    kk, jj, ii = np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij")
+    base = (ii + s * (jj + s * kk)).reshape(-1).astype(np.int64)
+    conn = np.empty((base.size, 8), dtype=np.int64)
+    for c in range(8):
+        di, dj, dk = c & 1, (c >> 1) & 1, (c >> 2) & 1
+        conn[:, c] = base + di + s * (dj + s * dk)
+    return conn.astype(np.int32)
+
+
+def hex_mesh(s: int = 128, seed: int = SEED_HEX, rng: Optional[np.random.Generator] = None) -> Mesh:
+    """Structured hex mesh: x, then B, then w are drawn from one generator."""
+    if rng is None:
+        rng = np.random.default_rng(seed)
+    N = s ** 3
+    E = max(s - 1, 0) ** 3
+    x = rng.uniform(-1.0, 1.0, N)
+    B = rng.standard_normal((E, 8))
+    w = rng.uniform(0.5, 1.5, E)
+    return Mesh(N, E, 8, hex_conn(s), B, w, x, f"hex{s}")
+
+
+def random_mesh(n_nodes: int, n_elems: int, k: int, seed: int) -> Mesh:
+    """Unstructured mesh with uniformly random connectivity (repeats allowed)."""
+    rng = np.random.default_rng(seed)
+    conn = rng.integers(0, max(n_nodes, 1), size=(n_elems, k)).astype(np.int32)
+    x = rng.uniform(-1.0, 1.0, n_nodes)
+    B = rng.standard_normal((n_elems, k))
+    w = rng.uniform(0.5, 1.5, n_elems)
+    return Mesh(n_nodes, n_elems, k, conn, B, w, x, f"rand{n_nodes}x{n_elems}x{k}")
+
+
+@dataclasses.dataclass
+class Dense:
+    A: np.ndarray  # (rows, cols) float64 row-major
+    x: np.ndarray  # (cols,)
+    w: np.ndarray  # (rows,)
+
+
+def dense(n: int = 10_000, seed: int = SEED_DENSE, rows: Optional[int] = None) -> Dense:
+    """A ~ N(0, 1/cols), then x ~ U(-1,1), then w ~ U(0.5,1.5)."""
+    rows = n if rows is None else rows
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((rows, n)) * (1.0 / np.sqrt(n))
+    x = rng.uniform(-1.0, 1.0, n)
+    w = rng.uniform(0.5, 1.5, rows)
+    return Dense(A, x, w)
+
+
+@dataclasses.dataclass
+class BatchedDense:
+    A: np.ndarray  # (m, m)
+    X: np.ndarray  # (m, n)
+    W: np.ndarray  # (m, n)
+
+
+def batched_dense(m: int = 4096, n: int = 1024, seed: int = SEED_BDENSE) -> BatchedDense:
+    """A ~ N(0, 1/m), then X ~ U(-1,1), then W ~ U(0.5,1.5)."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, m)) * (1.0 / np.sqrt(m))
+    X = rng.uniform(-1.0, 1.0, (m, n))
+    W = rng.uniform(0.5, 1.5, (m, n))
+    return BatchedDense(A, X, W)
+
+
+def fd_directions(shape, count: int = 16, seed: int = 33) -> np.ndarray:
+    """Random unit-norm directions for finite-difference checks."""
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal((count,) + tuple(shape))
+    norms = np.sqrt((d.reshape(count, -1) ** 2).sum(axis=1))
+    return d / norms.reshape((count,) + (1,) * len(shape))
+
+
+@dataclasses.dataclass
+class MeshBatch:
+    """Concatenated meshes. inst[i] = (n_nodes, n_elems, node_off, elem_off).
+
+    conn holds instance-local node numbers (0 <= conn < n_nodes of that
+    instance); B, w are concatenated over elements, x over nodes.
+    """
+
+    inst: np.ndarray  # int64 (n_inst, 4)
+    k: int
+    conn: np.ndarray  # int32 (E_total, k)
+    B: np.ndarray     # (E_total, k)
+    w: np.ndarray     # (E_total,)
+    x: np.ndarray     # (N_total,)
+    sides: np.ndarray
+
+    @property
+    def n_inst(self) -> int:
+        return int(self.inst.shape[0])
+
+    def instance(self, i: int) -> Mesh:
+        nn, ne, no, eo = (int(v) for v in self.inst[i])
+        return Mesh(nn, ne, self.k, self.conn[eo:eo + ne], self.B[eo:eo + ne],
+                    self.w[eo:eo + ne], self.x[no:no + nn], f"inst{i}")
+
+    def astype(self, dtype) -> "MeshBatch":
+        return MeshBatch(self.inst, self.k, self.conn, self.B.astype(dtype),
+                         self.w.astype(dtype), self.x.astype(dtype), self.sides)
+
+
+def uneven_sides(n_inst: int, seed: int = SEED_BATCH, lo: int = 10, hi: int = 100) -> np.ndarray:
+    """Side lengths log-uniform in [lo, hi]: s = round(lo * (hi/lo)**U)."""
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(0.0, 1.0, n_inst)
+    s = np.rint(lo * (hi / lo) ** u).astype(np.int64)
+    return s, rng
+
+
+def uneven_batch(n_inst: int = 256, seed: int = SEED_BATCH, lo: int = 10, hi: int = 100,
+                 sides: Optional[List[int]] = None) -> MeshBatch:
+    """Draw the sides, then for each instance x, B, w (same laws as hex_mesh)."""
+    s_arr, rng = uneven_sides(n_inst, seed, lo, hi)
+    if sides is not None:
+        s_arr = np.asarray(sides, dtype=np.int64)
+    conns, Bs, ws, xs = [], [], [], []
+    inst = np.zeros((len(s_arr), 4), dtype=np.int64)
+    no = eo = 0
+    for i, s in enumerate(s_arr):
+        m = hex_mesh(int(s), rng=rng)
+        inst[i] = (m.n_nodes, m.n_elems, no, eo)
+        no += m.n_nodes
+        eo += m.n_elems
+        conns.append(m.conn)
+        Bs.append(m.B)
+        ws.append(m.w)
+        xs.append(m.x)
+    conn = np.concatenate(conns) if conns else np.zeros((0, 8), np.int32)
+    B = np.concatenate(Bs) if Bs else np.zeros((0, 8))
+    w = np.concatenate(ws) if ws else np.zeros(0)
+    x = np.concatenate(xs) if xs else np.zeros(0)
+    return MeshBatch(inst, 8, conn, B, w, x, s_arr)
