@@ -1,0 +1,202 @@
+/*
+ * pgrad.h -- reverse-mode gradients of data-parallel scalar objectives on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates objectives of the shape studied in Liegeois, Kelley,
+ * Phipps, Rajamanickam and Vassilev, "Performance Portable Gradient
+ * Computations Using Source Transformation": a data-parallel gather
+ * (parallel_for), an element-wise nonlinearity, and a parallel sum
+ * (parallel_reduce / the parallel_sum builtin of section 3.2), together with
+ * their reverse-mode gradients: seed the result adjoint, broadcast it to every
+ * summand (reverse of a sum), multiply by the local derivative at the stored
+ * or recomputed forward value (section 4: the tape lives between kernels),
+ * and transpose every read of x into an accumulation into the shadow of x
+ * (section 3.1, view-access rule), which becomes an atomic update when the
+ * read index is itself a view entry (section 3.3, race detection).
+ *
+ *   psi(s)  = s^2/2 + log(1 + s^2)/2,   psi'(s) = s + s/(1 + s^2)
+ *
+ * CONVENTIONS
+ *   - Every pointer is DEVICE memory unless its comment says "host".
+ *   - Every call that takes a stream enqueues its work on that stream
+ *     (a hipStream_t passed as pg_stream; NULL is the legacy default stream)
+ *     and returns without waiting, except pg_bind_workspace, which waits.
+ *   - The caller owns every device buffer (inputs, outputs, workspace).  A
+ *     plan keeps NON-OWNING pointers to its constant operands (conn, B, w,
+ *     A, W); they must stay alive and unchanged while the plan is used.  The
+ *     library allocates no device memory; a plan owns only host memory.
+ *   - All arrays are dense row-major.  Index arrays are int32.
+ *   - Floating-point arrays are FP64 (PG_F64) or FP32 (PG_F32) as the plan's
+ *     dtype says; objective values f and the seeds fbar are always FP64, and
+ *     every reduction and accumulation is carried out in FP64.
+ *   - Gradients are taken with respect to x (or X) only; conn, B, w, A and W
+ *     are inactive (section 3.1: index metadata is never differentiated).
+ *   - Errors are reported as pg_status codes; argument errors are detected
+ *     before anything is enqueued and leave every output untouched.
+ *     pg_last_error() returns a thread-local message for the last non-OK
+ *     status.  No C++ exception crosses this interface.
+ *   - A plan must not be used concurrently from two streams: its workspace
+ *     holds per-call scratch (partial sums, counters, the stored tape).
+ */
+#ifndef PGRAD_H
+#define PGRAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PGRAD_VERSION 1
+#define PG_MAX_K 32           /* maximum nodes per element */
+#define PG_WORKSPACE_ALIGN 256 /* required alignment of the workspace */
+
+typedef struct pg_plan_s* pg_plan;
+typedef void* pg_stream; /* a hipStream_t */
+
+typedef enum {
+    PG_OK = 0,
+    PG_EINVAL = 1,       /* bad size, null pointer, bad option */
+    PG_ERANGE = 2,       /* connectivity entry outside [0, n_nodes) */
+    PG_EDTYPE = 3,       /* unknown dtype */
+    PG_EALIAS = 4,       /* an output overlaps an input or the workspace */
+    PG_EWORKSPACE = 5,   /* workspace missing, too small or misaligned */
+    PG_EHIP = 6,         /* a HIP runtime call or launch failed */
+    PG_EUNSUPPORTED = 7, /* valid request this plan kind does not offer */
+    PG_ESTATE = 8        /* plan used before pg_bind_workspace, or no tape stored */
+} pg_status;
+
+typedef enum { PG_F64 = 0, PG_F32 = 1 } pg_dtype;
+
+/* How the reverse pass accumulates x-bar (section 3.3 race rule; the
+ * conclusion's "reschedule the reverse threads" remedy). */
+typedef enum {
+    PG_ADJ_AUTO = 0,   /* library choice (currently PG_ADJ_ATOMIC) */
+    PG_ADJ_ATOMIC = 1, /* element-parallel scatter with FP64 atomic adds */
+    PG_ADJ_GATHER = 2, /* deterministic: node-parallel gather over the
+                          transposed (node -> element) connectivity */
+    PG_ADJ_COLOUR = 3  /* deterministic: element colour classes, one
+                          non-atomic pass per colour */
+} pg_adjoint_kind;
+
+/* What the forward pass keeps for the reverse pass (section 4: intermediates
+ * are recorded in views between kernels). */
+typedef enum {
+    PG_RECOMPUTE = 0, /* the reverse pass recomputes the gathered values */
+    PG_STORE = 1      /* pg_objective stores them in the workspace */
+} pg_ckpt;
+
+typedef struct {
+    int32_t adjoint;    /* pg_adjoint_kind */
+    int32_t ckpt;       /* pg_ckpt */
+    int32_t block;      /* threads per workgroup, 0 = default (multiple of 64, <= 1024) */
+    int32_t tile;       /* work items per thread, 0 = default (1, 2 or 4) */
+    int32_t accumulate; /* 0: gradients overwrite grad; 1: add into grad
+                           (the shadow-argument convention of the generated
+                           gradient in section 4) */
+} pg_options;
+
+/* One instance of a mesh batch: its nodes are x[node_off .. node_off+n_nodes)
+ * and its elements are rows elem_off .. elem_off+n_elems of conn, B and w.
+ * conn holds instance-local node numbers in [0, n_nodes). */
+typedef struct {
+    int64_t n_nodes;
+    int64_t n_elems;
+    int64_t node_off;
+    int64_t elem_off;
+} pg_instance;
+
+/* pg_options with every field at its default. */
+pg_options pg_default_options(void);
+
+/* ------------------------------------------------------------------ plans */
+
+/* Element-connectivity objective (the stencil example of section 4 written
+ * for a general connectivity table):
+ *   f(x) = sum_e w[e] * psi( u_e ),  u_e = sum_{j<k} B[e*k+j] * x[conn[e*k+j]]
+ *   grad = G^T ( fbar * w (.) psi'(G x) ),  G[e, conn[e,j]] += B[e,j]
+ * conn: n_elems*k int32, B: n_elems*k, w: n_elems (dtype), all device.
+ * 1 <= k <= PG_MAX_K; n_nodes < 2^31; n_elems*k < 2^31.
+ * *workspace_bytes (host, out) receives the workspace size this plan needs.
+ * *plan (host, out) is written only on PG_OK. */
+pg_status pg_mesh_plan(pg_plan* plan, int64_t n_nodes, int64_t n_elems, int32_t k,
+                       const int32_t* conn, const void* B, const void* w, pg_dtype dtype,
+                       const pg_options* opts, size_t* workspace_bytes);
+
+/* Dense row reduction (hierarchical team/vector parallelism, named as future
+ * work in the conclusion):  f(x) = sum_i w[i] psi((A x)_i),
+ * grad = A^T (fbar * w (.) psi'(A x)).  A: rows x cols, w: rows (dtype). */
+pg_status pg_dense_plan(pg_plan* plan, int64_t rows, int64_t cols, const void* A, const void* w,
+                        pg_dtype dtype, const pg_options* opts, size_t* workspace_bytes);
+
+/* Batched dense objective over the columns of X (m x n):
+ *   f(X) = sum_{i,j} W[i,j] psi((A X)_{ij}),  grad = A^T (fbar * W (.) psi'(A X)).
+ * A: m x m, W: m x n (dtype).  The contractions run on the matrix cores. */
+pg_status pg_bdense_plan(pg_plan* plan, int64_t m, int64_t n, const void* A, const void* W,
+                         pg_dtype dtype, const pg_options* opts, size_t* workspace_bytes);
+
+/* Many independent meshes in one launch.  inst (host) has n_inst entries;
+ * conn, B, w are the concatenations described by pg_instance.  Objectives
+ * are per instance: f_out and fbar have n_inst entries. */
+pg_status pg_mesh_batch_plan(pg_plan* plan, int32_t n_inst, const pg_instance* inst, int32_t k,
+                             const int32_t* conn, const void* B, const void* w, pg_dtype dtype,
+                             const pg_options* opts, size_t* workspace_bytes);
+
+/* Workspace size of a plan (host out). */
+pg_status pg_workspace_size(pg_plan plan, size_t* workspace_bytes);
+
+/* Bind a caller-owned device workspace of at least the queried size,
+ * aligned to PG_WORKSPACE_ALIGN, to the plan; validate the connectivity
+ * (PG_ERANGE if an entry is outside [0, n_nodes)) and build the plan's
+ * device structures (transposed connectivity, colour classes, work lists).
+ * Enqueued on stream and WAITS for it.  Rebinding is allowed. */
+pg_status pg_bind_workspace(pg_plan plan, void* workspace, size_t bytes, pg_stream stream);
+
+/* ------------------------------------------------------------- evaluation */
+
+/* f_out (device, FP64, 1 entry or n_inst for a batch) = f(x).
+ * With ckpt == PG_STORE the forward values are kept for pg_adjoint. */
+pg_status pg_objective(pg_plan plan, const void* x, double* f_out, pg_stream stream);
+
+/* One call, both passes (section 4's generated gradient: forward replay,
+ * seed 1, reverse pass): f_out = f(x) (may be NULL), grad = df/dx.
+ * grad has the shape of x and must not overlap x, the operands or the
+ * workspace. */
+pg_status pg_gradient(pg_plan plan, const void* x, void* grad, double* f_out, pg_stream stream);
+
+/* Reverse pass only, seeded with fbar (device FP64, 1 entry or n_inst):
+ * grad = fbar * df/dx.  With ckpt == PG_STORE it reads the values stored by
+ * the last pg_objective on the same x (PG_ESTATE if none was stored);
+ * with PG_RECOMPUTE it recomputes them from x. */
+pg_status pg_adjoint(pg_plan plan, const void* x, const double* fbar, void* grad,
+                     pg_stream stream);
+
+/* Hessian-vector product of the mesh objective (tangent over reverse,
+ * named as future work in the conclusion):
+ *   hv = G^T ( w (.) psi''(G x) (.) (G v) ).  Mesh plans only. */
+pg_status pg_hvp(pg_plan plan, const void* x, const void* v, void* hv, pg_stream stream);
+
+/* Measurement hook.  mode 0: off; 1: time the dominant kernel of every
+ * subsequent evaluation (the element pass of a mesh or batch, the fused row
+ * pass of a dense plan, the forward or backward product of a batched dense
+ * plan); 2: time each whole evaluation call.  Each timed launch records a
+ * pair of HIP events (owned by the plan, up to 4096 pairs) on the call's
+ * stream.  pg_timing_read waits for the last recorded event, returns the sum
+ * of the elapsed times (milliseconds, host out) and the number of timed
+ * launches (host out), and clears the record.  Enabling resets the record. */
+pg_status pg_timing(pg_plan plan, int32_t mode);
+pg_status pg_timing_read(pg_plan plan, double* total_ms, int64_t* count);
+
+pg_status pg_plan_destroy(pg_plan plan);
+
+/* Thread-local description of the last non-OK status ("" if none). */
+const char* pg_last_error(void);
+
+int pg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PGRAD_H */

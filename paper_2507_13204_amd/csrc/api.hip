@@ -1,0 +1,841 @@
+// C ABI of the gradient library: plan construction, argument validation,
+// workspace layout and dispatch to the HIP kernels.  Host code only.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "../../include/pgrad.h"
+#include "launch.hpp"
+
+using namespace pg;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+pg_status fail(pg_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+#define PG_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) return fail(PG_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+enum Kind { K_MESH = 1, K_DENSE = 2, K_BDENSE = 3, K_BATCH = 4 };
+
+constexpr size_t kAlign = PG_WORKSPACE_ALIGN;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t total = 0;
+    size_t take(size_t bytes) {
+        const size_t off = total;
+        total += align_up(bytes);
+        return off;
+    }
+};
+
+size_t esize(pg_dtype d) { return d == PG_F64 ? 8 : 4; }
+
+bool overlap(const void* a, size_t an, const void* b, size_t bn) {
+    if (!a || !b || an == 0 || bn == 0) return false;
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + bn && b0 < a0 + an;
+}
+
+constexpr size_t NONE = ~size_t(0);
+
+}  // namespace
+
+struct pg_plan_s {
+    Kind kind;
+    pg_dtype dtype;
+    pg_options opt;
+    // mesh / batch
+    MeshView mesh;
+    int64_t mesh_blocks_n = 0;
+    // batch
+    BatchView batch;
+    std::vector<pg_instance> inst;
+    int64_t n_nodes_total = 0, n_elems_total = 0;
+    std::vector<int64_t> h_tile_inst, h_tile_first, h_tile_slot, h_node_off, h_elem_end, h_seg;
+    int batch_grid = 0;
+    // dense
+    DenseView dense;
+    int dense_groups = 0;
+    bool dense_fused = false;
+    // batched dense
+    BDenseView bd;
+    int64_t bd_tiles = 0;
+    // workspace
+    size_t ws_bytes = 0;
+    size_t o_partials = NONE, o_flag = NONE, o_u = NONE, o_v = NONE, o_offs = NONE,
+           o_cursor = NONE, o_inc = NONE, o_scan = NONE, o_gacc = NONE, o_colpart = NONE,
+           o_tiles = NONE, o_vmat = NONE;
+    size_t n_partials = 0;
+    char* ws = nullptr;
+    bool bound = false;
+    bool tape_valid = false;
+    const void* tape_x = nullptr;
+    // measurement hook
+    int32_t timing_mode = 0;
+    std::vector<hipEvent_t> ev;  // pairs: ev[2i] start, ev[2i+1] stop
+    int64_t ev_n = 0;
+
+    template <typename P>
+    P* at(size_t off) const {
+        return off == NONE ? nullptr : reinterpret_cast<P*>(ws + off);
+    }
+};
+
+namespace {
+
+pg_status check_opts(const pg_options* o, pg_options* out) {
+    *out = pg_default_options();
+    if (o) *out = *o;
+    if (out->adjoint < PG_ADJ_AUTO || out->adjoint > PG_ADJ_COLOUR)
+        return fail(PG_EINVAL, "options.adjoint %d is not a pg_adjoint_kind", out->adjoint);
+    if (out->adjoint == PG_ADJ_AUTO) out->adjoint = PG_ADJ_ATOMIC;
+    if (out->ckpt != PG_RECOMPUTE && out->ckpt != PG_STORE)
+        return fail(PG_EINVAL, "options.ckpt %d is not a pg_ckpt", out->ckpt);
+    if (out->block == 0) out->block = 256;
+    if (out->block < 64 || out->block > 1024 || out->block % 64)
+        return fail(PG_EINVAL, "options.block %d must be a multiple of 64 in [64, 1024]",
+                    out->block);
+    if (out->tile == 0) out->tile = 1;
+    if (out->tile != 1 && out->tile != 2 && out->tile != 4)
+        return fail(PG_EINVAL, "options.tile %d must be 1, 2 or 4", out->tile);
+    if (out->accumulate != 0 && out->accumulate != 1)
+        return fail(PG_EINVAL, "options.accumulate must be 0 or 1");
+    return PG_OK;
+}
+
+pg_status check_dtype(pg_dtype d) {
+    if (d != PG_F64 && d != PG_F32) return fail(PG_EDTYPE, "dtype %d is not PG_F64 or PG_F32", (int)d);
+    return PG_OK;
+}
+
+bool k_in_registers(int32_t k) { return k == 2 || k == 4 || k == 8; }
+
+pg_plan_s* new_plan(Kind kind, pg_dtype dt, const pg_options& o) {
+    pg_plan_s* p = new (std::nothrow) pg_plan_s();
+    if (!p) return nullptr;
+    p->kind = kind;
+    p->dtype = dt;
+    p->opt = o;
+    return p;
+}
+
+// ------------------------------------------------------------- mesh layout
+
+void layout_mesh(pg_plan_s* p) {
+    Layout L;
+    const MeshView& m = p->mesh;
+    const int ept = k_in_registers(m.k) ? p->opt.tile : 1;
+    p->opt.tile = ept;
+    p->mesh_blocks_n = mesh_blocks(m.n_elems, p->opt.block, ept);
+    p->n_partials = (size_t)std::max<int64_t>(p->mesh_blocks_n, 1);
+    p->o_partials = L.take(sizeof(double) * p->n_partials);
+    p->o_flag = L.take(sizeof(int32_t) * 4);
+    if (p->opt.ckpt == PG_STORE) p->o_u = L.take(sizeof(double) * (size_t)m.n_elems);
+    if (p->opt.adjoint == PG_ADJ_GATHER) {
+        p->o_v = L.take(sizeof(double) * (size_t)m.n_elems);
+        p->o_offs = L.take(sizeof(int32_t) * (size_t)(m.n_nodes + 1));
+        p->o_cursor = L.take(sizeof(int32_t) * (size_t)m.n_nodes);
+        p->o_inc = L.take(sizeof(int32_t) * (size_t)(m.n_elems * m.k));
+        p->o_scan = L.take(sizeof(int64_t) * (size_t)scan_scratch_items(m.n_nodes));
+    }
+    // FP32 gradients accumulate in an FP64 buffer before rounding once.
+    if (p->dtype == PG_F32) p->o_gacc = L.take(sizeof(double) * (size_t)m.n_nodes);
+    p->ws_bytes = L.total;
+}
+
+// ------------------------------------------------------------ batch layout
+
+void layout_batch(pg_plan_s* p) {
+    Layout L;
+    const int te = p->opt.block * p->opt.tile;
+    p->batch.tile_elems = te;
+    // Work list: tiles of every instance, largest instance first (LPT), then
+    // by instance index and tile index, dealt round-robin to a persistent grid.
+    const int32_t ni = (int32_t)p->inst.size();
+    std::vector<int32_t> order(ni);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return p->inst[a].n_elems > p->inst[b].n_elems;
+    });
+    p->h_seg.assign(ni + 1, 0);
+    for (int32_t i = 0; i < ni; ++i)
+        p->h_seg[i + 1] = p->h_seg[i] + (p->inst[i].n_elems + te - 1) / te;
+    const int64_t nt = p->h_seg[ni];
+    p->h_tile_inst.clear();
+    p->h_tile_first.clear();
+    p->h_tile_slot.clear();
+    for (int32_t oi : order) {
+        const pg_instance& in = p->inst[oi];
+        const int64_t tiles = (in.n_elems + te - 1) / te;
+        for (int64_t t = 0; t < tiles; ++t) {
+            p->h_tile_inst.push_back(oi);
+            p->h_tile_first.push_back(in.elem_off + t * te);
+            p->h_tile_slot.push_back(p->h_seg[oi] + t);
+        }
+    }
+    p->h_node_off.resize(ni);
+    p->h_elem_end.resize(ni);
+    for (int32_t i = 0; i < ni; ++i) {
+        p->h_node_off[i] = p->inst[i].node_off;
+        p->h_elem_end[i] = p->inst[i].elem_off + p->inst[i].n_elems;
+    }
+    p->batch.n_tiles = nt;
+    p->n_partials = (size_t)std::max<int64_t>(nt, 1);
+    p->o_partials = L.take(sizeof(double) * p->n_partials);
+    p->o_flag = L.take(sizeof(int32_t) * 4);
+    // tables: tile_inst, tile_first, tile_slot (nt each), node_off, elem_end (ni), seg (ni+1)
+    p->o_tiles = L.take(sizeof(int64_t) * (size_t)(3 * nt + 3 * ni + 1));
+    if (p->opt.ckpt == PG_STORE) p->o_u = L.take(sizeof(double) * (size_t)p->n_elems_total);
+    if (p->dtype == PG_F32) p->o_gacc = L.take(sizeof(double) * (size_t)p->n_nodes_total);
+    p->ws_bytes = L.total;
+    // 256 compute units; 8 resident workgroups of 256 threads per CU at most.
+    const int64_t cap = 256LL * std::max(1, 2048 / p->opt.block);
+    p->batch_grid = (int)std::max<int64_t>(1, std::min<int64_t>(nt, cap));
+}
+
+// ------------------------------------------------------------ dense layout
+
+void layout_dense(pg_plan_s* p) {
+    Layout L;
+    const DenseView& d = p->dense;
+    const int64_t vn = p->dtype == PG_F64 ? 2 : 4;
+    p->dense_fused = d.cols <= dense_fused_max_cols() * (p->dtype == PG_F64 ? 1 : 2) && d.cols % vn == 0;
+    p->dense_groups = (int)std::max<int64_t>(1, std::min<int64_t>(d.rows, 256));
+    p->n_partials = (size_t)std::max<int64_t>(std::max<int64_t>(d.rows, p->dense_groups), 1);
+    p->o_partials = L.take(sizeof(double) * p->n_partials);
+    p->o_flag = L.take(sizeof(int32_t) * 4);
+    p->o_v = L.take(sizeof(double) * (size_t)std::max<int64_t>(d.rows, 1));
+    if (p->dense_fused)
+        p->o_colpart = L.take(sizeof(double) * (size_t)p->dense_groups * (size_t)d.cols);
+    p->ws_bytes = L.total;
+}
+
+void layout_bdense(pg_plan_s* p) {
+    Layout L;
+    p->bd_tiles = bdense_fwd_tiles(p->bd.m, p->bd.n);
+    p->n_partials = (size_t)std::max<int64_t>(p->bd_tiles, 1);
+    p->o_partials = L.take(sizeof(double) * p->n_partials);
+    p->o_flag = L.take(sizeof(int32_t) * 4);
+    // V = W (.) psi'(A X) in the plan dtype: the stored tape (PG_STORE) or the
+    // recomputed operand of the backward product.
+    p->o_vmat = L.take(esize(p->dtype) * (size_t)p->bd.m * (size_t)p->bd.n);
+    p->ws_bytes = L.total;
+}
+
+pg_status need_bound(pg_plan p) {
+    if (!p) return fail(PG_EINVAL, "plan is NULL");
+    if (!p->bound) return fail(PG_ESTATE, "plan has no workspace bound (call pg_bind_workspace)");
+    return PG_OK;
+}
+
+constexpr int64_t kMaxTimed = 4096;
+
+// Record the start (or stop) event of a timed launch at this level.
+hipError_t tmark(pg_plan p, int level, bool start, hipStream_t s) {
+    if (p->timing_mode != level || p->ev_n >= kMaxTimed) return hipSuccess;
+    hipError_t e = hipEventRecord(p->ev[2 * p->ev_n + (start ? 0 : 1)], s);
+    if (!start && e == hipSuccess) ++p->ev_n;
+    return e;
+}
+
+size_t x_bytes(pg_plan p) {
+    switch (p->kind) {
+        case K_MESH: return esize(p->dtype) * (size_t)p->mesh.n_nodes;
+        case K_BATCH: return esize(p->dtype) * (size_t)p->n_nodes_total;
+        case K_DENSE: return esize(p->dtype) * (size_t)p->dense.cols;
+        case K_BDENSE: return esize(p->dtype) * (size_t)(p->bd.m * p->bd.n);
+    }
+    return 0;
+}
+
+size_t f_count(pg_plan p) { return p->kind == K_BATCH ? p->inst.size() : 1; }
+
+// Operands a result must not overlap.
+pg_status check_out_alias(pg_plan p, const void* out, size_t out_bytes, const void* x,
+                          const char* what) {
+    if (overlap(out, out_bytes, x, x_bytes(p))) return fail(PG_EALIAS, "%s overlaps x", what);
+    if (overlap(out, out_bytes, p->ws, p->ws_bytes))
+        return fail(PG_EALIAS, "%s overlaps the workspace", what);
+    const size_t es = esize(p->dtype);
+    switch (p->kind) {
+        case K_MESH:
+        case K_BATCH: {
+            const int64_t E = p->kind == K_MESH ? p->mesh.n_elems : p->n_elems_total;
+            const int32_t k = p->kind == K_MESH ? p->mesh.k : p->batch.k;
+            const void* conn = p->kind == K_MESH ? (const void*)p->mesh.conn : (const void*)p->batch.conn;
+            const void* B = p->kind == K_MESH ? p->mesh.B : p->batch.B;
+            const void* w = p->kind == K_MESH ? p->mesh.w : p->batch.w;
+            if (overlap(out, out_bytes, conn, 4 * (size_t)(E * k)) ||
+                overlap(out, out_bytes, B, es * (size_t)(E * k)) ||
+                overlap(out, out_bytes, w, es * (size_t)E))
+                return fail(PG_EALIAS, "%s overlaps conn, B or w", what);
+            break;
+        }
+        case K_DENSE:
+            if (overlap(out, out_bytes, p->dense.A, es * (size_t)(p->dense.rows * p->dense.cols)) ||
+                overlap(out, out_bytes, p->dense.w, es * (size_t)p->dense.rows))
+                return fail(PG_EALIAS, "%s overlaps A or w", what);
+            break;
+        case K_BDENSE:
+            if (overlap(out, out_bytes, p->bd.A, es * (size_t)(p->bd.m * p->bd.m)) ||
+                overlap(out, out_bytes, p->bd.W, es * (size_t)(p->bd.m * p->bd.n)))
+                return fail(PG_EALIAS, "%s overlaps A or W", what);
+            break;
+    }
+    return PG_OK;
+}
+
+MeshPass base_pass(pg_plan p, const void* x) {
+    MeshPass q;
+    q.x = x;
+    q.partials = p->at<double>(p->o_partials);
+    q.block = p->opt.block;
+    q.ept = p->opt.tile;
+    return q;
+}
+
+// ------------------------------------------------------------ mesh driver
+
+enum Want { W_OBJ = 1, W_GRAD = 2 };
+
+pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, double* f_out,
+                   int want, hipStream_t s) {
+    const MeshView& m = p->mesh;
+    MeshPass q = base_pass(p, x);
+    const bool f32 = p->dtype == PG_F32;
+    const bool acc = p->opt.accumulate != 0;
+    const bool obj = (want & W_OBJ) != 0;
+    const bool grd = (want & W_GRAD) != 0;
+    if (!grd) {
+        q.u_store = p->at<double>(p->o_u);
+        PG_HIP(tmark(p, 1, true, s));
+        PG_HIP(launch_mesh_elem(m, M_PRIMAL, q, s));
+        PG_HIP(tmark(p, 1, false, s));
+        if (f_out) PG_HIP(launch_final_sum(q.partials, p->mesh_blocks_n, f_out, s));
+        if (q.u_store) {
+            p->tape_valid = true;
+            p->tape_x = x;
+        }
+        return PG_OK;
+    }
+    q.fbar = fbar;
+    if (!obj && p->opt.ckpt == PG_STORE) {
+        if (!p->tape_valid) return fail(PG_ESTATE, "no stored forward values: call pg_objective first");
+        q.u_in = p->at<double>(p->o_u);
+    }
+    if (p->opt.adjoint == PG_ADJ_GATHER) {
+        q.v_out = p->at<double>(p->o_v);
+        PG_HIP(tmark(p, 1, true, s));
+        PG_HIP(launch_mesh_elem(m, obj ? M_GRAD_V : M_ADJ_V, q, s));
+        PG_HIP(launch_mesh_node_gather(m, p->at<int32_t>(p->o_offs), p->at<int32_t>(p->o_inc),
+                                       q.v_out, grad, acc, 256, s));
+        PG_HIP(tmark(p, 1, false, s));
+    } else {  // atomic
+        if (f32) {
+            q.gacc = p->at<double>(p->o_gacc);
+            PG_HIP(launch_zero(q.gacc, sizeof(double) * (size_t)m.n_nodes, s));
+        } else {
+            q.gacc = static_cast<double*>(grad);
+            if (!acc) PG_HIP(launch_zero(grad, sizeof(double) * (size_t)m.n_nodes, s));
+        }
+        PG_HIP(tmark(p, 1, true, s));
+        PG_HIP(launch_mesh_elem(m, obj ? M_GRAD_ATOMIC : M_ADJ_ATOMIC, q, s));
+        PG_HIP(tmark(p, 1, false, s));
+        if (f32)
+            PG_HIP(launch_f64_to_f32(q.gacc, static_cast<float*>(grad), m.n_nodes, acc, s));
+    }
+    if (obj && f_out) PG_HIP(launch_final_sum(q.partials, p->mesh_blocks_n, f_out, s));
+    return PG_OK;
+}
+
+pg_status mesh_bind(pg_plan p, hipStream_t s) {
+    const MeshView& m = p->mesh;
+    int32_t* flag = p->at<int32_t>(p->o_flag);
+    PG_HIP(launch_zero(flag, sizeof(int32_t) * 4, s));
+    const int64_t items = m.n_elems * m.k;
+    if (p->opt.adjoint == PG_ADJ_GATHER) {
+        int32_t* cnt = p->at<int32_t>(p->o_cursor);
+        PG_HIP(launch_zero(cnt, sizeof(int32_t) * (size_t)m.n_nodes, s));
+        PG_HIP(launch_validate_count(m.conn, items, m.n_nodes, cnt, flag, s));
+    } else {
+        PG_HIP(launch_validate_count(m.conn, items, m.n_nodes, nullptr, flag, s));
+    }
+    int32_t hflag = 0;
+    PG_HIP(hipMemcpyAsync(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    if (hflag) return fail(PG_ERANGE, "connectivity has an entry outside [0, %lld)", (long long)m.n_nodes);
+    if (p->opt.adjoint == PG_ADJ_GATHER) {
+        int32_t* offs = p->at<int32_t>(p->o_offs);
+        PG_HIP(launch_exclusive_scan(p->at<int32_t>(p->o_cursor), m.n_nodes, offs,
+                                     p->at<int64_t>(p->o_scan), s));
+        PG_HIP(launch_csr_fill_sort(m.conn, items, m.n_nodes, offs, p->at<int32_t>(p->o_cursor),
+                                    p->at<int32_t>(p->o_inc), s));
+        PG_HIP(hipStreamSynchronize(s));
+    }
+    return PG_OK;
+}
+
+// ----------------------------------------------------------- batch driver
+
+pg_status batch_bind(pg_plan p, hipStream_t s) {
+    int32_t* flag = p->at<int32_t>(p->o_flag);
+    PG_HIP(launch_zero(flag, sizeof(int32_t) * 4, s));
+    // Validate each instance's connectivity against its own node count.
+    for (const pg_instance& in : p->inst) {
+        if (in.n_elems == 0) continue;
+        PG_HIP(launch_validate_count(p->batch.conn + in.elem_off * p->batch.k,
+                                     in.n_elems * p->batch.k, in.n_nodes, nullptr, flag, s));
+    }
+    // Upload the work list and instance tables.
+    const int64_t nt = p->batch.n_tiles, ni = (int64_t)p->inst.size();
+    std::vector<int64_t> tab;
+    tab.reserve((size_t)(3 * nt + 3 * ni + 1));
+    tab.insert(tab.end(), p->h_tile_inst.begin(), p->h_tile_inst.end());
+    tab.insert(tab.end(), p->h_tile_first.begin(), p->h_tile_first.end());
+    tab.insert(tab.end(), p->h_tile_slot.begin(), p->h_tile_slot.end());
+    tab.insert(tab.end(), p->h_node_off.begin(), p->h_node_off.end());
+    tab.insert(tab.end(), p->h_elem_end.begin(), p->h_elem_end.end());
+    tab.insert(tab.end(), p->h_seg.begin(), p->h_seg.end());
+    int64_t* dtab = p->at<int64_t>(p->o_tiles);
+    if (!tab.empty())
+        PG_HIP(hipMemcpyAsync(dtab, tab.data(), sizeof(int64_t) * tab.size(),
+                              hipMemcpyHostToDevice, s));
+    int32_t hflag = 0;
+    PG_HIP(hipMemcpyAsync(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    if (hflag) return fail(PG_ERANGE, "an instance's connectivity has an entry outside its node range");
+    p->batch.tile_inst = dtab;
+    p->batch.tile_first = dtab + nt;
+    p->batch.tile_slot = dtab + 2 * nt;
+    p->batch.inst_node_off = dtab + 3 * nt;
+    p->batch.inst_elem_end = dtab + 3 * nt + ni;
+    return PG_OK;
+}
+
+pg_status batch_run(pg_plan p, const void* x, const double* fbar, void* grad, double* f_out,
+                    int want, hipStream_t s) {
+    const bool f32 = p->dtype == PG_F32;
+    const bool acc = p->opt.accumulate != 0;
+    const bool obj = (want & W_OBJ) != 0;
+    const bool grd = (want & W_GRAD) != 0;
+    const int64_t ni = (int64_t)p->inst.size();
+    const int64_t* seg = p->at<int64_t>(p->o_tiles) + 3 * p->batch.n_tiles + 2 * ni;
+    BatchPass q;
+    q.x = x;
+    q.partials = p->at<double>(p->o_partials);
+    q.grid = p->batch_grid;
+    q.block = p->opt.block;
+    q.fbar = fbar;
+    if (!grd) {
+        q.u_store = p->at<double>(p->o_u);
+        PG_HIP(tmark(p, 1, true, s));
+        PG_HIP(launch_batch_persistent(p->batch, B_PRIMAL, q, s));
+        PG_HIP(tmark(p, 1, false, s));
+        if (f_out) PG_HIP(launch_segmented_sum(q.partials, seg, ni, f_out, s));
+        if (q.u_store) {
+            p->tape_valid = true;
+            p->tape_x = x;
+        }
+        return PG_OK;
+    }
+    if (!obj && p->opt.ckpt == PG_STORE) {
+        if (!p->tape_valid) return fail(PG_ESTATE, "no stored forward values: call pg_objective first");
+        q.u_in = p->at<double>(p->o_u);
+    }
+    if (f32) {
+        q.grad = p->at<double>(p->o_gacc);
+        PG_HIP(launch_zero(q.grad, sizeof(double) * (size_t)p->n_nodes_total, s));
+    } else {
+        q.grad = grad;
+        if (!acc) PG_HIP(launch_zero(grad, sizeof(double) * (size_t)p->n_nodes_total, s));
+    }
+    PG_HIP(tmark(p, 1, true, s));
+    PG_HIP(launch_batch_persistent(p->batch, obj ? B_GRAD_ATOMIC : B_ADJ_ATOMIC, q, s));
+    PG_HIP(tmark(p, 1, false, s));
+    if (f32)
+        PG_HIP(launch_f64_to_f32((const double*)q.grad, static_cast<float*>(grad),
+                                 p->n_nodes_total, acc, s));
+    if (obj && f_out) PG_HIP(launch_segmented_sum(q.partials, seg, ni, f_out, s));
+    return PG_OK;
+}
+
+// ----------------------------------------------------------- dense driver
+
+pg_status dense_run(pg_plan p, const void* x, const double* fbar, void* grad, double* f_out,
+                    int want, hipStream_t s) {
+    const DenseView& d = p->dense;
+    double* partials = p->at<double>(p->o_partials);
+    const bool grd = (want & W_GRAD) != 0;
+    const bool obj = (want & W_OBJ) != 0;
+    const Dtype dt = p->dtype == PG_F64 ? F64 : F32;
+    if (d.rows == 0 || d.cols == 0) {
+        // f = sum over no rows (or psi(0) = 0 on every row) and a zero gradient.
+        if (grd && !p->opt.accumulate) PG_HIP(launch_zero(grad, esize(p->dtype) * (size_t)d.cols, s));
+        if (f_out && obj) PG_HIP(launch_final_sum(partials, 0, f_out, s));
+        return PG_OK;
+    }
+    // The fused kernel reads x with 16-byte vector loads.
+    if (p->dense_fused && ((uintptr_t)x % 16) == 0) {
+        PG_HIP(tmark(p, 1, true, s));
+        PG_HIP(launch_dense_fused(d, x, fbar, grd ? 1 : 0, partials, p->at<double>(p->o_colpart),
+                                  p->dense_groups, s));
+        PG_HIP(tmark(p, 1, false, s));
+        if (grd)
+            PG_HIP(launch_dense_colsum(p->at<double>(p->o_colpart), p->dense_groups, d.cols, grad,
+                                       dt, p->opt.accumulate, s));
+        if (f_out && obj) PG_HIP(launch_final_sum(partials, p->dense_groups, f_out, s));
+    } else {
+        double* v = grd ? p->at<double>(p->o_v) : nullptr;
+        PG_HIP(tmark(p, 1, true, s));
+        PG_HIP(launch_dense_rows(d, x, fbar, partials, v, s));
+        PG_HIP(tmark(p, 1, false, s));
+        if (grd) PG_HIP(launch_dense_cols(d, v, grad, p->opt.accumulate, s));
+        if (f_out && obj) PG_HIP(launch_final_sum(partials, d.rows, f_out, s));
+    }
+    return PG_OK;
+}
+
+// --------------------------------------------------- batched dense driver
+
+pg_status bdense_run(pg_plan p, const void* X, const double* fbar, void* G, double* f_out,
+                     int want, hipStream_t s) {
+    double* partials = p->at<double>(p->o_partials);
+    void* V = p->ws + p->o_vmat;
+    const bool grd = (want & W_GRAD) != 0;
+    const bool obj = (want & W_OBJ) != 0;
+    if (!grd) {
+        const bool store = p->opt.ckpt == PG_STORE;
+        PG_HIP(tmark(p, 1, true, s));
+        PG_HIP(launch_bdense_fwd(p->bd, X, partials, store ? V : nullptr, s));
+        PG_HIP(tmark(p, 1, false, s));
+        if (f_out) PG_HIP(launch_final_sum(partials, p->bd_tiles, f_out, s));
+        if (store) {
+            p->tape_valid = true;
+            p->tape_x = X;
+        }
+        return PG_OK;
+    }
+    if (obj || p->opt.ckpt == PG_RECOMPUTE) {
+        PG_HIP(launch_bdense_fwd(p->bd, X, partials, V, s));
+        if (obj && f_out) PG_HIP(launch_final_sum(partials, p->bd_tiles, f_out, s));
+    } else if (!p->tape_valid) {
+        return fail(PG_ESTATE, "no stored forward values: call pg_objective first");
+    }
+    PG_HIP(tmark(p, 1, true, s));
+    PG_HIP(launch_bdense_bwd(p->bd, V, fbar, G, p->opt.accumulate, s));
+    PG_HIP(tmark(p, 1, false, s));
+    return PG_OK;
+}
+
+pg_status run_kind(pg_plan p, const void* x, const double* fbar, void* grad, double* f_out,
+                   int want, hipStream_t s) {
+    switch (p->kind) {
+        case K_MESH: return mesh_run(p, x, fbar, grad, f_out, want, s);
+        case K_BATCH: return batch_run(p, x, fbar, grad, f_out, want, s);
+        case K_DENSE: return dense_run(p, x, fbar, grad, f_out, want, s);
+        case K_BDENSE: return bdense_run(p, x, fbar, grad, f_out, want, s);
+    }
+    return fail(PG_EINVAL, "unknown plan kind");
+}
+
+pg_status run(pg_plan p, const void* x, const double* fbar, void* grad, double* f_out, int want,
+              pg_stream stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    PG_HIP(tmark(p, 2, true, s));
+    pg_status st = run_kind(p, x, fbar, grad, f_out, want, s);
+    if (st != PG_OK) return st;
+    PG_HIP(tmark(p, 2, false, s));
+    return PG_OK;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+
+extern "C" {
+
+pg_options pg_default_options(void) {
+    pg_options o;
+    o.adjoint = PG_ADJ_AUTO;
+    o.ckpt = PG_RECOMPUTE;
+    o.block = 0;
+    o.tile = 0;
+    o.accumulate = 0;
+    return o;
+}
+
+const char* pg_last_error(void) { return g_err; }
+
+int pg_version(void) { return PGRAD_VERSION; }
+
+pg_status pg_mesh_plan(pg_plan* plan, int64_t n_nodes, int64_t n_elems, int32_t k,
+                       const int32_t* conn, const void* B, const void* w, pg_dtype dtype,
+                       const pg_options* opts, size_t* workspace_bytes) {
+    g_err[0] = 0;
+    if (!plan || !workspace_bytes) return fail(PG_EINVAL, "plan and workspace_bytes must not be NULL");
+    pg_status st = check_dtype(dtype);
+    if (st) return st;
+    pg_options o;
+    if ((st = check_opts(opts, &o))) return st;
+    if (o.adjoint == PG_ADJ_COLOUR) return fail(PG_EUNSUPPORTED, "colour adjoint is not available for mesh plans yet");
+    if (n_nodes < 0 || n_elems < 0) return fail(PG_EINVAL, "n_nodes and n_elems must be >= 0");
+    if (k < 1 || k > PG_MAX_K) return fail(PG_EINVAL, "k = %d outside [1, %d]", k, PG_MAX_K);
+    if (n_nodes >= (1LL << 31) || n_elems * (int64_t)k >= (1LL << 31))
+        return fail(PG_EINVAL, "sizes exceed the int32 index range");
+    if (n_elems > 0 && (!conn || !B || !w)) return fail(PG_EINVAL, "conn, B and w must not be NULL");
+    if (n_elems > 0 && n_nodes == 0) return fail(PG_ERANGE, "elements reference nodes but n_nodes is 0");
+    if (((uintptr_t)conn % 16) || ((uintptr_t)B % 16) || ((uintptr_t)w % 8))
+        return fail(PG_EINVAL, "conn and B must be 16-byte aligned, w 8-byte aligned");
+    pg_plan_s* p = new_plan(K_MESH, dtype, o);
+    if (!p) return fail(PG_EINVAL, "out of host memory");
+    p->mesh.n_nodes = n_nodes;
+    p->mesh.n_elems = n_elems;
+    p->mesh.k = k;
+    p->mesh.dtype = dtype == PG_F64 ? F64 : F32;
+    p->mesh.conn = conn;
+    p->mesh.B = B;
+    p->mesh.w = w;
+    layout_mesh(p);
+    *workspace_bytes = p->ws_bytes;
+    *plan = p;
+    return PG_OK;
+}
+
+pg_status pg_mesh_batch_plan(pg_plan* plan, int32_t n_inst, const pg_instance* inst, int32_t k,
+                             const int32_t* conn, const void* B, const void* w, pg_dtype dtype,
+                             const pg_options* opts, size_t* workspace_bytes) {
+    g_err[0] = 0;
+    if (!plan || !workspace_bytes) return fail(PG_EINVAL, "plan and workspace_bytes must not be NULL");
+    pg_status st = check_dtype(dtype);
+    if (st) return st;
+    pg_options o;
+    if ((st = check_opts(opts, &o))) return st;
+    if (o.adjoint != PG_ADJ_ATOMIC) return fail(PG_EUNSUPPORTED, "mesh batches use the atomic adjoint");
+    if (n_inst < 0 || (n_inst > 0 && !inst)) return fail(PG_EINVAL, "bad instance table");
+    if (k < 1 || k > PG_MAX_K) return fail(PG_EINVAL, "k = %d outside [1, %d]", k, PG_MAX_K);
+    int64_t nn = 0, ne = 0;
+    for (int32_t i = 0; i < n_inst; ++i) {
+        const pg_instance& in = inst[i];
+        if (in.n_nodes < 0 || in.n_elems < 0 || in.node_off < 0 || in.elem_off < 0)
+            return fail(PG_EINVAL, "instance %d has a negative size or offset", i);
+        if (in.n_nodes >= (1LL << 31)) return fail(PG_EINVAL, "instance %d too large", i);
+        if (in.n_elems > 0 && in.n_nodes == 0)
+            return fail(PG_ERANGE, "instance %d has elements but no nodes", i);
+        nn = std::max(nn, in.node_off + in.n_nodes);
+        ne = std::max(ne, in.elem_off + in.n_elems);
+    }
+    if (ne * (int64_t)k >= (1LL << 31) || nn >= (1LL << 31))
+        return fail(PG_EINVAL, "sizes exceed the int32 index range");
+    if (ne > 0 && (!conn || !B || !w)) return fail(PG_EINVAL, "conn, B and w must not be NULL");
+    if (((uintptr_t)conn % 16) || ((uintptr_t)B % 16) || ((uintptr_t)w % 8))
+        return fail(PG_EINVAL, "conn and B must be 16-byte aligned, w 8-byte aligned");
+    pg_plan_s* p = new_plan(K_BATCH, dtype, o);
+    if (!p) return fail(PG_EINVAL, "out of host memory");
+    p->inst.assign(inst, inst + n_inst);
+    p->n_nodes_total = nn;
+    p->n_elems_total = ne;
+    p->batch.n_inst = n_inst;
+    p->batch.k = k;
+    p->batch.dtype = dtype == PG_F64 ? F64 : F32;
+    p->batch.conn = conn;
+    p->batch.B = B;
+    p->batch.w = w;
+    if (!k_in_registers(k)) p->opt.tile = 1;
+    layout_batch(p);
+    *workspace_bytes = p->ws_bytes;
+    *plan = p;
+    return PG_OK;
+}
+
+pg_status pg_dense_plan(pg_plan* plan, int64_t rows, int64_t cols, const void* A, const void* w,
+                        pg_dtype dtype, const pg_options* opts, size_t* workspace_bytes) {
+    g_err[0] = 0;
+    if (!plan || !workspace_bytes) return fail(PG_EINVAL, "plan and workspace_bytes must not be NULL");
+    pg_status st = check_dtype(dtype);
+    if (st) return st;
+    pg_options o;
+    if ((st = check_opts(opts, &o))) return st;
+    if (rows < 0 || cols < 0) return fail(PG_EINVAL, "rows and cols must be >= 0");
+    if (rows >= (1LL << 31) || cols >= (1LL << 31)) return fail(PG_EINVAL, "sizes exceed the int32 range");
+    if (rows > 0 && cols > 0 && (!A || !w)) return fail(PG_EINVAL, "A and w must not be NULL");
+    if ((uintptr_t)A % 16) return fail(PG_EINVAL, "A must be 16-byte aligned");
+    pg_plan_s* p = new_plan(K_DENSE, dtype, o);
+    if (!p) return fail(PG_EINVAL, "out of host memory");
+    p->dense.rows = rows;
+    p->dense.cols = cols;
+    p->dense.dtype = dtype == PG_F64 ? F64 : F32;
+    p->dense.A = A;
+    p->dense.w = w;
+    layout_dense(p);
+    *workspace_bytes = p->ws_bytes;
+    *plan = p;
+    return PG_OK;
+}
+
+pg_status pg_bdense_plan(pg_plan* plan, int64_t m, int64_t n, const void* A, const void* W,
+                         pg_dtype dtype, const pg_options* opts, size_t* workspace_bytes) {
+    g_err[0] = 0;
+    if (!plan || !workspace_bytes) return fail(PG_EINVAL, "plan and workspace_bytes must not be NULL");
+    pg_status st = check_dtype(dtype);
+    if (st) return st;
+    pg_options o;
+    if ((st = check_opts(opts, &o))) return st;
+    if (m < 0 || n < 0) return fail(PG_EINVAL, "m and n must be >= 0");
+    if (m >= (1LL << 31) || n >= (1LL << 31) || m * n >= (1LL << 40))
+        return fail(PG_EINVAL, "sizes exceed the supported range");
+    if (m > 0 && (!A || (n > 0 && !W))) return fail(PG_EINVAL, "A and W must not be NULL");
+    if (((uintptr_t)A % 16) || ((uintptr_t)W % 16)) return fail(PG_EINVAL, "A and W must be 16-byte aligned");
+    pg_plan_s* p = new_plan(K_BDENSE, dtype, o);
+    if (!p) return fail(PG_EINVAL, "out of host memory");
+    p->bd.m = m;
+    p->bd.n = n;
+    p->bd.dtype = dtype == PG_F64 ? F64 : F32;
+    p->bd.A = A;
+    p->bd.W = W;
+    layout_bdense(p);
+    *workspace_bytes = p->ws_bytes;
+    *plan = p;
+    return PG_OK;
+}
+
+pg_status pg_workspace_size(pg_plan plan, size_t* workspace_bytes) {
+    if (!plan || !workspace_bytes) return fail(PG_EINVAL, "plan and workspace_bytes must not be NULL");
+    *workspace_bytes = plan->ws_bytes;
+    return PG_OK;
+}
+
+pg_status pg_bind_workspace(pg_plan p, void* workspace, size_t bytes, pg_stream stream) {
+    g_err[0] = 0;
+    if (!p) return fail(PG_EINVAL, "plan is NULL");
+    if (p->ws_bytes > 0 && !workspace) return fail(PG_EWORKSPACE, "workspace is NULL");
+    if (bytes < p->ws_bytes)
+        return fail(PG_EWORKSPACE, "workspace has %zu bytes, the plan needs %zu", bytes, p->ws_bytes);
+    if ((uintptr_t)workspace % kAlign)
+        return fail(PG_EWORKSPACE, "workspace must be %zu-byte aligned", kAlign);
+    p->ws = static_cast<char*>(workspace);
+    p->bound = false;
+    p->tape_valid = false;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    pg_status st = PG_OK;
+    switch (p->kind) {
+        case K_MESH: st = mesh_bind(p, s); break;
+        case K_BATCH: st = batch_bind(p, s); break;
+        case K_DENSE:
+        case K_BDENSE: break;
+    }
+    if (st == PG_OK) p->bound = true;
+    return st;
+}
+
+pg_status pg_objective(pg_plan p, const void* x, double* f_out, pg_stream stream) {
+    g_err[0] = 0;
+    pg_status st = need_bound(p);
+    if (st) return st;
+    if (!x && x_bytes(p) > 0) return fail(PG_EINVAL, "x is NULL");
+    if (!f_out) return fail(PG_EINVAL, "f_out is NULL");
+    if ((st = check_out_alias(p, f_out, sizeof(double) * f_count(p), x, "f_out"))) return st;
+    return run(p, x, nullptr, nullptr, f_out, W_OBJ, stream);
+}
+
+pg_status pg_gradient(pg_plan p, const void* x, void* grad, double* f_out, pg_stream stream) {
+    g_err[0] = 0;
+    pg_status st = need_bound(p);
+    if (st) return st;
+    if ((!x || !grad) && x_bytes(p) > 0) return fail(PG_EINVAL, "x and grad must not be NULL");
+    if ((st = check_out_alias(p, grad, x_bytes(p), x, "grad"))) return st;
+    if (f_out && (st = check_out_alias(p, f_out, sizeof(double) * f_count(p), x, "f_out"))) return st;
+    if (overlap(f_out, sizeof(double) * f_count(p), grad, x_bytes(p)))
+        return fail(PG_EALIAS, "f_out overlaps grad");
+    return run(p, x, nullptr, grad, f_out, W_OBJ | W_GRAD, stream);
+}
+
+pg_status pg_adjoint(pg_plan p, const void* x, const double* fbar, void* grad, pg_stream stream) {
+    g_err[0] = 0;
+    pg_status st = need_bound(p);
+    if (st) return st;
+    if ((!x || !grad) && x_bytes(p) > 0) return fail(PG_EINVAL, "x and grad must not be NULL");
+    if (!fbar) return fail(PG_EINVAL, "fbar is NULL");
+    if ((st = check_out_alias(p, grad, x_bytes(p), x, "grad"))) return st;
+    if (overlap(fbar, sizeof(double) * f_count(p), grad, x_bytes(p)))
+        return fail(PG_EALIAS, "fbar overlaps grad");
+    return run(p, x, fbar, grad, nullptr, W_GRAD, stream);
+}
+
+pg_status pg_hvp(pg_plan p, const void* x, const void* v, void* hv, pg_stream stream) {
+    g_err[0] = 0;
+    pg_status st = need_bound(p);
+    if (st) return st;
+    if (p->kind != K_MESH) return fail(PG_EUNSUPPORTED, "pg_hvp supports mesh plans only");
+    if ((!x || !v || !hv) && x_bytes(p) > 0) return fail(PG_EINVAL, "x, v and hv must not be NULL");
+    if ((st = check_out_alias(p, hv, x_bytes(p), x, "hv"))) return st;
+    if (overlap(hv, x_bytes(p), v, x_bytes(p))) return fail(PG_EALIAS, "hv overlaps v");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const MeshView& m = p->mesh;
+    MeshPass q = base_pass(p, x);
+    q.xd = v;
+    const bool f32 = p->dtype == PG_F32;
+    q.gacc = f32 ? p->at<double>(p->o_gacc) : static_cast<double*>(hv);
+    if (f32 || !p->opt.accumulate) PG_HIP(launch_zero(q.gacc, sizeof(double) * (size_t)m.n_nodes, s));
+    PG_HIP(launch_mesh_elem(m, M_HVP, q, s));
+    if (f32) PG_HIP(launch_f64_to_f32(q.gacc, static_cast<float*>(hv), m.n_nodes, p->opt.accumulate, s));
+    return PG_OK;
+}
+
+pg_status pg_timing(pg_plan p, int32_t mode) {
+    if (!p) return fail(PG_EINVAL, "plan is NULL");
+    if (mode < 0 || mode > 2) return fail(PG_EINVAL, "timing mode %d not in {0, 1, 2}", mode);
+    if (mode != 0 && p->ev.empty()) {
+        p->ev.resize(2 * kMaxTimed);
+        for (auto& e : p->ev) PG_HIP(hipEventCreate(&e));
+    }
+    p->timing_mode = mode;
+    p->ev_n = 0;
+    return PG_OK;
+}
+
+pg_status pg_timing_read(pg_plan p, double* total_ms, int64_t* count) {
+    if (!p || !total_ms || !count) return fail(PG_EINVAL, "NULL argument");
+    double tot = 0.0;
+    if (p->ev_n > 0) {
+        PG_HIP(hipEventSynchronize(p->ev[2 * (p->ev_n - 1) + 1]));
+        for (int64_t i = 0; i < p->ev_n; ++i) {
+            float ms = 0.f;
+            PG_HIP(hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]));
+            tot += ms;
+        }
+    }
+    *total_ms = tot;
+    *count = p->ev_n;
+    p->ev_n = 0;
+    return PG_OK;
+}
+
+pg_status pg_plan_destroy(pg_plan p) {
+    if (p) {
+        for (auto& e : p->ev) (void)hipEventDestroy(e);
+    }
+    delete p;
+    return PG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,215 @@
+// Batched dense objective on the matrix cores:
+//   forward   Y = A X,  f = sum W (.) psi(Y)  (epilogue),  V = W (.) psi'(Y)
+//   backward  G = fbar * A^T V
+//
+// Both products are m x m by m x n contractions, tiled 128 x 128 x 16 per
+// workgroup of four waves; each wave owns a 64 x 64 block of C as 4 x 4
+// MFMA 16x16x4 accumulators (FP64: v_mfma_f64_16x16x4_f64; FP32:
+// v_mfma_f32_16x16x4_f32, whose accumulation inside the instruction is FP32).
+// Tiles are staged k-major in LDS (double buffered, the next tile prefetched
+// into registers while the current one feeds the matrix cores).  The
+// nonlinearity and its derivative are fused into the forward epilogue, so
+// neither Y nor psi(Y) round-trips through HBM; the objective is reduced per
+// tile and then in a fixed order (deterministic).
+#include "device_common.hpp"
+#include "launch.hpp"
+
+namespace pg {
+
+namespace {
+
+constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int NTHR = 256;
+constexpr int PAD = 4;  // LDS row padding (elements) against bank conflicts on transposed stores
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+
+template <>
+struct Mfma<double> {
+    using acc_t = d4;
+    __device__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+    __device__ static acc_t mac(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static double get(const acc_t& c, int r) { return c[r]; }
+};
+
+template <>
+struct Mfma<float> {
+    using acc_t = f4;
+    __device__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+    __device__ static acc_t mac(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static double get(const acc_t& c, int r) { return (double)c[r]; }
+};
+
+// Elements of one operand tile each thread moves per k-step.
+constexpr int kPerThread = BM * BK / NTHR;  // 8
+
+enum Epi { EPI_FWD = 0, EPI_BWD = 1 };
+
+// C[M x N] = op(A)[M x K] * Bm[K x N].
+//   TRANS_A == false: op(A)[i][k] = A[i * lda + k]   (forward, A is m x m)
+//   TRANS_A == true:  op(A)[i][k] = A[k * lda + i]   (backward, A^T)
+template <typename T, bool TRANS_A, int EPI>
+__global__ void __launch_bounds__(NTHR)
+k_gemm_mfma(const T* __restrict__ A, const T* __restrict__ Bm, int64_t M, int64_t N, int64_t K,
+            const T* __restrict__ W, double* __restrict__ partials, T* __restrict__ Vout,
+            const double* __restrict__ fbar, T* __restrict__ Gout, int accumulate) {
+    using MF = Mfma<T>;
+    using acc_t = typename MF::acc_t;
+    __shared__ T As[2][BK][BM + PAD];
+    __shared__ T Bs[2][BK][BN + PAD];
+    __shared__ double red[NTHR / kWave];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int wm = wid >> 1, wn = wid & 1;  // wave's 64 x 64 block within the tile
+    const int64_t i0 = (int64_t)blockIdx.y * BM, j0 = (int64_t)blockIdx.x * BN;
+
+    // Global -> register staging of one k-tile.
+    T ra[kPerThread], rb[kPerThread];
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+        for (int q = 0; q < kPerThread; ++q) {
+            const int p = tid + NTHR * q;  // 0 .. 2047
+            // A tile: element (i, k) with i in [0,BM), k in [0,BK)
+            int ii, kk;
+            if (TRANS_A) {  // contiguous along i in memory
+                kk = p / BM;
+                ii = p % BM;
+            } else {  // contiguous along k in memory
+                ii = p / BK;
+                kk = p % BK;
+            }
+            const int64_t gi = i0 + ii, gk = k0 + kk;
+            T va = T(0);
+            if (gi < M && gk < K) va = TRANS_A ? A[gk * K + gi] : A[gi * K + gk];
+            ra[q] = va;
+            // B tile: element (k, j), contiguous along j
+            const int bk = p / BN, bj = p % BN;
+            const int64_t gk2 = k0 + bk, gj = j0 + bj;
+            rb[q] = (gk2 < K && gj < N) ? Bm[gk2 * N + gj] : T(0);
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < kPerThread; ++q) {
+            const int p = tid + NTHR * q;
+            int ii, kk;
+            if (TRANS_A) {
+                kk = p / BM;
+                ii = p % BM;
+            } else {
+                ii = p / BK;
+                kk = p % BK;
+            }
+            As[buf][kk][ii] = ra[q];
+            Bs[buf][p / BN][p % BN] = rb[q];
+        }
+    };
+
+    acc_t acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = MF::zero();
+
+    const int64_t nk = (K + BK - 1) / BK;
+    if (nk > 0) {
+        gload(0);
+        lstore(0);
+    }
+    __syncthreads();
+    const int li = lane & 15, lk = lane >> 4;
+    for (int64_t t = 0; t < nk; ++t) {
+        const int buf = (int)(t & 1);
+        if (t + 1 < nk) gload((t + 1) * BK);
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks) {
+            T a[4], b[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                a[x] = As[buf][ks * 4 + lk][wm * 64 + x * 16 + li];
+                b[x] = Bs[buf][ks * 4 + lk][wn * 64 + x * 16 + li];
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[x][y] = MF::mac(a[x], b[y], acc[x][y]);
+        }
+        if (t + 1 < nk) lstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    // Accumulator (x, y) register r of lane l holds C[row][col] with
+    // row = x*16 + 4*(l/16) + r and col = y*16 + l%16 inside the wave block.
+    double tsum = 0.0;
+    const double fb = (EPI == EPI_BWD && fbar) ? fbar[0] : 1.0;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t gi = i0 + wm * 64 + x * 16 + 4 * lk + r;
+                const int64_t gj = j0 + wn * 64 + y * 16 + li;
+                if (gi < M && gj < N) {
+                    const double c = MF::get(acc[x][y], r);
+                    const int64_t o = gi * N + gj;
+                    if constexpr (EPI == EPI_FWD) {
+                        const double s2 = c * c, wv = to_f64(W[o]);
+                        tsum += wv * psi_from_sq(s2);
+                        if (Vout) Vout[o] = static_cast<T>(wv * dpsi_from(c, s2));
+                    } else {
+                        const double g = fb * c;
+                        Gout[o] = accumulate ? static_cast<T>(to_f64(Gout[o]) + g) : static_cast<T>(g);
+                    }
+                }
+            }
+    if constexpr (EPI == EPI_FWD) {
+        const double s = block_sum<NTHR>(tsum, red);
+        if (tid == 0) partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+}  // namespace
+
+int64_t bdense_fwd_tiles(int64_t m, int64_t n) { return ((m + BM - 1) / BM) * ((n + BN - 1) / BN); }
+
+hipError_t launch_bdense_fwd(const BDenseView& b, const void* X, double* partials, void* V,
+                             hipStream_t s) {
+    if (b.m == 0 || b.n == 0) return hipSuccess;
+    const dim3 grid((unsigned)((b.n + BN - 1) / BN), (unsigned)((b.m + BM - 1) / BM));
+    if (b.dtype == F64)
+        hipLaunchKernelGGL((k_gemm_mfma<double, false, EPI_FWD>), grid, dim3(NTHR), 0, s,
+                           (const double*)b.A, (const double*)X, b.m, b.n, b.m, (const double*)b.W,
+                           partials, (double*)V, nullptr, nullptr, 0);
+    else
+        hipLaunchKernelGGL((k_gemm_mfma<float, false, EPI_FWD>), grid, dim3(NTHR), 0, s,
+                           (const float*)b.A, (const float*)X, b.m, b.n, b.m, (const float*)b.W,
+                           partials, (float*)V, nullptr, nullptr, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_bdense_bwd(const BDenseView& b, const void* V, const double* fbar, void* G,
+                             int accumulate, hipStream_t s) {
+    if (b.m == 0 || b.n == 0) return hipSuccess;
+    const dim3 grid((unsigned)((b.n + BN - 1) / BN), (unsigned)((b.m + BM - 1) / BM));
+    if (b.dtype == F64)
+        hipLaunchKernelGGL((k_gemm_mfma<double, true, EPI_BWD>), grid, dim3(NTHR), 0, s,
+                           (const double*)b.A, (const double*)V, b.m, b.n, b.m, nullptr, nullptr,
+                           nullptr, fbar, (double*)G, accumulate);
+    else
+        hipLaunchKernelGGL((k_gemm_mfma<float, true, EPI_BWD>), grid, dim3(NTHR), 0, s,
+                           (const float*)b.A, (const float*)V, b.m, b.n, b.m, nullptr, nullptr,
+                           nullptr, fbar, (float*)G, accumulate);
+    return hipGetLastError();
+}
+
+}  // namespace pg

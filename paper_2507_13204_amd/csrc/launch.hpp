@@ -1,0 +1,171 @@
+// Internal host-side launchers of the HIP kernels (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pg {
+
+enum Dtype { F64 = 0, F32 = 1 };
+
+// ------------------------------------------------------------------ meshes
+
+// What one element-parallel pass computes.
+enum MeshMode {
+    M_PRIMAL = 0,       // u_e, t_e = w_e psi(u_e), per-block partial sums of t
+    M_GRAD_ATOMIC = 1,  // primal + v_e = fbar w_e psi'(u_e) scattered with atomics
+    M_GRAD_V = 2,       // primal + v_e written out (for the node-parallel gather)
+    M_ADJ_ATOMIC = 3,   // v_e scattered with atomics, no objective
+    M_ADJ_V = 4,        // v_e written out, no objective
+    M_HVP = 5,          // c_e = w_e psi''(u_e) (G d)_e scattered with atomics
+    M_GRAD_COLOUR = 6,  // primal + v_e scattered with plain read-add-write
+    M_ADJ_COLOUR = 7    // v_e scattered with plain read-add-write, no objective
+};
+
+struct MeshView {
+    int64_t n_nodes = 0;
+    int64_t n_elems = 0;
+    int32_t k = 0;
+    Dtype dtype = F64;
+    const int32_t* conn = nullptr;
+    const void* B = nullptr;
+    const void* w = nullptr;
+};
+
+struct MeshPass {
+    const void* x = nullptr;       // node values (dtype)
+    const void* xd = nullptr;      // direction for M_HVP (dtype)
+    const double* u_in = nullptr;  // stored u (replaces the gather when set)
+    double* u_store = nullptr;     // store u here when set
+    double* v_out = nullptr;       // per-element v for M_*_V
+    double* gacc = nullptr;        // FP64 accumulation target (atomic / colour modes)
+    const double* fbar = nullptr;  // device seed (nullptr means 1)
+    double* partials = nullptr;    // per-block partial sums of t
+    const int32_t* elist = nullptr;  // element list (colour passes); nullptr = all
+    int64_t elist_n = 0;
+    int64_t partial_base = 0;      // first partial slot of this launch
+    int block = 256;
+    int ept = 1;
+};
+
+// Number of workgroups an element pass over n items launches.
+int64_t mesh_blocks(int64_t n_items, int block, int ept);
+
+hipError_t launch_mesh_elem(const MeshView& m, MeshMode mode, const MeshPass& p, hipStream_t s);
+
+// Node-parallel gather of the reverse pass over the transposed connectivity:
+// g[n] (+)= sum_{p in offs[n]..offs[n+1]} v[inc[p]/k] * B[inc[p]].
+hipError_t launch_mesh_node_gather(const MeshView& m, const int32_t* offs, const int32_t* inc,
+                                   const double* v, void* grad, int accumulate, int block,
+                                   hipStream_t s);
+
+// out[0] (=|+=) sum of partials[0..n) in a fixed order (one workgroup).
+hipError_t launch_final_sum(const double* partials, int64_t n, double* out, hipStream_t s);
+
+// Segmented: out[i] = sum partials[seg[i]..seg[i+1]) for i < nseg.
+hipError_t launch_segmented_sum(const double* partials, const int64_t* seg, int64_t nseg,
+                                double* out, hipStream_t s);
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
+// dst (FP32) (=|+=) src (FP64).
+hipError_t launch_f64_to_f32(const double* src, float* dst, int64_t n, int accumulate,
+                             hipStream_t s);
+// dst (FP64) += src (FP64).
+hipError_t launch_add_f64(const double* src, double* dst, int64_t n, hipStream_t s);
+
+// Plan-time structures.
+// flag |= 1 if any conn entry is outside [0, n_nodes); cnt[node] += 1 when cnt.
+hipError_t launch_validate_count(const int32_t* conn, int64_t n_items, int64_t n_nodes,
+                                 int32_t* cnt, int32_t* flag, hipStream_t s);
+// Exclusive scan: out[0..n] with out[n] = total.  scratch holds
+// scan_scratch_items(n) int64 values.
+int64_t scan_scratch_items(int64_t n);
+hipError_t launch_exclusive_scan(const int32_t* in, int64_t n, int32_t* out, int64_t* scratch,
+                                 hipStream_t s);
+// inc[cursor[conn[i]]++] = i, then each row of inc sorted ascending.
+hipError_t launch_csr_fill_sort(const int32_t* conn, int64_t n_items, int64_t n_nodes,
+                                const int32_t* offs, int32_t* cursor, int32_t* inc, hipStream_t s);
+
+// ---------------------------------------------------------------- batches
+
+struct BatchView {
+    int32_t n_inst = 0;
+    int32_t k = 0;
+    Dtype dtype = F64;
+    const int32_t* conn = nullptr;
+    const void* B = nullptr;
+    const void* w = nullptr;
+    // device tables
+    const int64_t* tile_inst = nullptr;   // instance of each tile (work-list order)
+    const int64_t* tile_first = nullptr;  // first global element of each tile
+    const int64_t* tile_slot = nullptr;   // partial slot of each tile (instance-major)
+    const int64_t* inst_node_off = nullptr;
+    const int64_t* inst_elem_end = nullptr;  // one past the last element of the instance
+    int64_t n_tiles = 0;
+    int tile_elems = 0;                   // elements per tile
+};
+
+enum BatchMode { B_PRIMAL = 0, B_GRAD_ATOMIC = 1, B_ADJ_ATOMIC = 2 };
+
+struct BatchPass {
+    const void* x = nullptr;
+    void* grad = nullptr;          // FP64 accumulation target
+    const double* fbar = nullptr;  // per instance (nullptr means 1)
+    double* partials = nullptr;    // one slot per tile
+    const double* u_in = nullptr;
+    double* u_store = nullptr;
+    int grid = 0;                  // persistent workgroups
+    int block = 256;
+};
+
+hipError_t launch_batch_persistent(const BatchView& b, BatchMode mode, const BatchPass& p,
+                                   hipStream_t s);
+
+// ------------------------------------------------------------------ dense
+
+struct DenseView {
+    int64_t rows = 0, cols = 0;
+    Dtype dtype = F64;
+    const void* A = nullptr;
+    const void* w = nullptr;
+};
+
+// Fused single pass over A: per row r_i = A_i . x (workgroup reduction),
+// t_i, v_i = fbar w_i psi'(r_i); colpart[g, :] = sum over the rows of
+// workgroup g of v_i A_i.  partials[g] = sum of t over its rows.
+// Returns hipErrorInvalidValue if cols exceed the register-resident limit.
+int64_t dense_fused_max_cols();
+hipError_t launch_dense_fused(const DenseView& d, const void* x, const double* fbar, int want_grad,
+                              double* partials, double* colpart, int ngroups, hipStream_t s);
+// grad[j] (=|+=) sum_g colpart[g, j] in fixed order (dtype of grad).
+hipError_t launch_dense_colsum(const double* colpart, int ngroups, int64_t cols, void* grad,
+                               Dtype dt, int accumulate, hipStream_t s);
+// Two-pass fallback: r = A x per row (one workgroup per row), v stored.
+hipError_t launch_dense_rows(const DenseView& d, const void* x, const double* fbar,
+                             double* partials, double* v, hipStream_t s);
+// grad (=|+=) A^T v (column-parallel).
+hipError_t launch_dense_cols(const DenseView& d, const double* v, void* grad, int accumulate,
+                             hipStream_t s);
+
+// --------------------------------------------------------- batched dense
+
+struct BDenseView {
+    int64_t m = 0, n = 0;
+    Dtype dtype = F64;
+    const void* A = nullptr;
+    const void* W = nullptr;
+};
+
+// Forward: Y = A X on the matrix cores with the epilogue
+// t = W psi(Y) (per-tile partial sums) and, when V != nullptr,
+// V = W psi'(Y) (FP64 or dtype per vdt).
+int64_t bdense_fwd_tiles(int64_t m, int64_t n);
+hipError_t launch_bdense_fwd(const BDenseView& b, const void* X, double* partials, void* V,
+                             hipStream_t s);
+// Backward: G (=|+=) fbar * A^T V.
+hipError_t launch_bdense_bwd(const BDenseView& b, const void* V, const double* fbar, void* G,
+                             int accumulate, hipStream_t s);
+
+}  // namespace pg

@@ -1,0 +1,406 @@
+"""Python binding of libpgrad.so (argument marshalling only).
+
+Every entry point of the C ABI (include/pgrad.h) is reachable under the same
+name through :func:`lib`; the classes below own a plan and its workspace and
+pass torch tensors' device pointers and the current HIP stream.  All the
+arithmetic happens in the library's HIP kernels: if the library is missing
+or cannot be loaded, every call raises :class:`PgError` -- there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpgrad.so")
+
+# pg_status
+OK, EINVAL, ERANGE, EDTYPE, EALIAS, EWORKSPACE, EHIP, EUNSUPPORTED, ESTATE = range(9)
+STATUS_NAMES = ["PG_OK", "PG_EINVAL", "PG_ERANGE", "PG_EDTYPE", "PG_EALIAS", "PG_EWORKSPACE",
+                "PG_EHIP", "PG_EUNSUPPORTED", "PG_ESTATE"]
+F64, F32 = 0, 1
+ADJ_AUTO, ADJ_ATOMIC, ADJ_GATHER, ADJ_COLOUR = 0, 1, 2, 3
+RECOMPUTE, STORE = 0, 1
+WORKSPACE_ALIGN = 256
+
+ADJOINTS = {"auto": ADJ_AUTO, "atomic": ADJ_ATOMIC, "gather": ADJ_GATHER, "colour": ADJ_COLOUR}
+CKPTS = {"recompute": RECOMPUTE, "store": STORE}
+
+EXPORTS = ("pg_default_options", "pg_mesh_plan", "pg_dense_plan", "pg_bdense_plan",
+           "pg_mesh_batch_plan", "pg_workspace_size", "pg_bind_workspace", "pg_objective",
+           "pg_gradient", "pg_adjoint", "pg_hvp", "pg_timing", "pg_timing_read",
+           "pg_plan_destroy", "pg_last_error", "pg_version")
+
+
+class PgError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str = ""):
+        name = STATUS_NAMES[code] if 0 <= code < len(STATUS_NAMES) else str(code)
+        super().__init__(f"{where}: {name}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("adjoint", ctypes.c_int32), ("ckpt", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("accumulate", ctypes.c_int32)]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_elems", ctypes.c_int64),
+                ("node_off", ctypes.c_int64), ("elem_off", ctypes.c_int64)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_SZP = ctypes.POINTER(ctypes.c_size_t)
+_PLANP = ctypes.POINTER(ctypes.c_void_p)
+
+
+def lib():
+    """Load libpgrad.so (built by paper_2507_13204_amd.build); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise PgError(EHIP, "load", f"{LIB_PATH} is missing: build it with "
+                      "`python -m paper_2507_13204_amd.build` (no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    L.pg_default_options.restype = Options
+    L.pg_default_options.argtypes = []
+    OP = ctypes.POINTER(Options)
+    L.pg_mesh_plan.argtypes = [_PLANP, _I64, _I64, _I32, _VP, _VP, _VP, ctypes.c_int, OP, _SZP]
+    L.pg_dense_plan.argtypes = [_PLANP, _I64, _I64, _VP, _VP, ctypes.c_int, OP, _SZP]
+    L.pg_bdense_plan.argtypes = [_PLANP, _I64, _I64, _VP, _VP, ctypes.c_int, OP, _SZP]
+    L.pg_mesh_batch_plan.argtypes = [_PLANP, _I32, ctypes.POINTER(Instance), _I32, _VP, _VP, _VP,
+                                     ctypes.c_int, OP, _SZP]
+    L.pg_workspace_size.argtypes = [_VP, _SZP]
+    L.pg_bind_workspace.argtypes = [_VP, _VP, ctypes.c_size_t, _VP]
+    L.pg_objective.argtypes = [_VP, _VP, _VP, _VP]
+    L.pg_gradient.argtypes = [_VP, _VP, _VP, _VP, _VP]
+    L.pg_adjoint.argtypes = [_VP, _VP, _VP, _VP, _VP]
+    L.pg_hvp.argtypes = [_VP, _VP, _VP, _VP, _VP]
+    L.pg_plan_destroy.argtypes = [_VP]
+    L.pg_timing.argtypes = [_VP, _I32]
+    L.pg_timing_read.argtypes = [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]
+    L.pg_last_error.restype = ctypes.c_char_p
+    L.pg_last_error.argtypes = []
+    L.pg_version.restype = ctypes.c_int
+    L.pg_version.argtypes = []
+    for name in ("pg_mesh_plan", "pg_dense_plan", "pg_bdense_plan", "pg_mesh_batch_plan",
+                 "pg_workspace_size", "pg_bind_workspace", "pg_objective", "pg_gradient",
+                 "pg_adjoint", "pg_hvp", "pg_timing", "pg_timing_read", "pg_plan_destroy"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(code: int, where: str):
+    if code != OK:
+        raise PgError(code, where, lib().pg_last_error().decode(errors="replace"))
+
+
+def make_options(adjoint="auto", ckpt="recompute", block: int = 0, tile: int = 0,
+                 accumulate: bool = False) -> Options:
+    o = Options()
+    o.adjoint = ADJOINTS[adjoint] if isinstance(adjoint, str) else int(adjoint)
+    o.ckpt = CKPTS[ckpt] if isinstance(ckpt, str) else int(ckpt)
+    o.block = int(block)
+    o.tile = int(tile)
+    o.accumulate = int(bool(accumulate))
+    return o
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise PgError(EDTYPE, "dtype", f"unsupported tensor dtype {t.dtype}")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise PgError(EINVAL, "tensor", "operands must be contiguous CUDA (HIP) tensors")
+
+
+class _Plan:
+    """Owns a pg_plan and the workspace tensor bound to it."""
+
+    def __init__(self):
+        self._plan = ctypes.c_void_p()
+        self._ws = None
+        self.workspace_bytes = 0
+
+    def _bind(self, device, stream=None):
+        nbytes = self.workspace_bytes
+        if nbytes > 0:
+            raw = torch.empty(nbytes + WORKSPACE_ALIGN, dtype=torch.uint8, device=device)
+            off = (-raw.data_ptr()) % WORKSPACE_ALIGN
+            self._ws_raw = raw
+            self._ws = raw[off:off + nbytes]
+            ptr = ctypes.c_void_p(self._ws.data_ptr())
+        else:
+            ptr = None
+        check(lib().pg_bind_workspace(self._plan, ptr, nbytes, _stream(stream)), "pg_bind_workspace")
+
+    def close(self):
+        if self._plan:
+            lib().pg_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def timing(self, mode: int):
+        """0 off, 1 time the dominant kernel of each call, 2 time each call."""
+        check(lib().pg_timing(self._plan, int(mode)), "pg_timing")
+
+    def timing_read(self) -> Tuple[float, int]:
+        """(total milliseconds, number of timed launches) since the last read."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        check(lib().pg_timing_read(self._plan, ctypes.byref(ms), ctypes.byref(n)), "pg_timing_read")
+        return ms.value, n.value
+
+    # generic calls -----------------------------------------------------
+    def _objective(self, x, f_shape, stream=None):
+        f = torch.empty(f_shape, dtype=torch.float64, device=x.device)
+        check(lib().pg_objective(self._plan, _ptr(x), _ptr(f), _stream(stream)), "pg_objective")
+        return f
+
+    def _gradient(self, x, f_shape, out=None, want_f=True, stream=None):
+        g = torch.empty_like(x) if out is None else out
+        f = torch.empty(f_shape, dtype=torch.float64, device=x.device) if want_f else None
+        check(lib().pg_gradient(self._plan, _ptr(x), _ptr(g), _ptr(f), _stream(stream)),
+              "pg_gradient")
+        return f, g
+
+    def _adjoint(self, x, fbar, out=None, stream=None):
+        g = torch.empty_like(x) if out is None else out
+        check(lib().pg_adjoint(self._plan, _ptr(x), _ptr(fbar), _ptr(g), _stream(stream)),
+              "pg_adjoint")
+        return g
+
+
+class MeshObjective(_Plan):
+    """f(x) = sum_e w_e psi(sum_j B[e,j] x[conn[e,j]]) and its gradient."""
+
+    def __init__(self, conn: torch.Tensor, B: torch.Tensor, w: torch.Tensor, n_nodes: int,
+                 adjoint="auto", ckpt="recompute", block: int = 0, tile: int = 0,
+                 accumulate: bool = False, stream=None):
+        super().__init__()
+        _need_cuda(conn, B, w)
+        if conn.dtype != torch.int32:
+            raise PgError(EINVAL, "MeshObjective", "conn must be int32")
+        E = conn.shape[0] if conn.dim() == 2 else 0
+        k = conn.shape[1] if conn.dim() == 2 else 1
+        self.conn, self.B, self.w = conn, B, w
+        self.n_nodes, self.n_elems, self.k = int(n_nodes), int(E), int(k)
+        self.dtype = B.dtype
+        self.options = make_options(adjoint, ckpt, block, tile, accumulate)
+        sz = ctypes.c_size_t()
+        check(lib().pg_mesh_plan(ctypes.byref(self._plan), self.n_nodes, E, k, _ptr(conn),
+                                 _ptr(B), _ptr(w), _dtype_code(B), ctypes.byref(self.options),
+                                 ctypes.byref(sz)), "pg_mesh_plan")
+        self.workspace_bytes = sz.value
+        self._bind(conn.device, stream)
+
+    def objective(self, x, stream=None):
+        _need_cuda(x)
+        return self._objective(x, (), stream)
+
+    def gradient(self, x, out=None, want_f=True, stream=None):
+        _need_cuda(x, out)
+        return self._gradient(x, (), out, want_f, stream)
+
+    def adjoint(self, x, fbar, out=None, stream=None):
+        _need_cuda(x, fbar, out)
+        return self._adjoint(x, fbar, out, stream)
+
+    def hvp(self, x, v, out=None, stream=None):
+        _need_cuda(x, v, out)
+        h = torch.empty_like(x) if out is None else out
+        check(lib().pg_hvp(self._plan, _ptr(x), _ptr(v), _ptr(h), _stream(stream)), "pg_hvp")
+        return h
+
+
+class DenseObjective(_Plan):
+    """f(x) = sum_i w_i psi((A x)_i) and its gradient."""
+
+    def __init__(self, A: torch.Tensor, w: torch.Tensor, accumulate: bool = False, stream=None):
+        super().__init__()
+        _need_cuda(A, w)
+        self.A, self.w = A, w
+        self.rows, self.cols = int(A.shape[0]), int(A.shape[1])
+        self.options = make_options(accumulate=accumulate)
+        sz = ctypes.c_size_t()
+        check(lib().pg_dense_plan(ctypes.byref(self._plan), self.rows, self.cols, _ptr(A), _ptr(w),
+                                  _dtype_code(A), ctypes.byref(self.options), ctypes.byref(sz)),
+              "pg_dense_plan")
+        self.workspace_bytes = sz.value
+        self._bind(A.device, stream)
+
+    def objective(self, x, stream=None):
+        _need_cuda(x)
+        return self._objective(x, (), stream)
+
+    def gradient(self, x, out=None, want_f=True, stream=None):
+        _need_cuda(x, out)
+        return self._gradient(x, (), out, want_f, stream)
+
+    def adjoint(self, x, fbar, out=None, stream=None):
+        _need_cuda(x, fbar, out)
+        return self._adjoint(x, fbar, out, stream)
+
+
+class BatchedDense(_Plan):
+    """f(X) = sum W (.) psi(A X) with both products on the matrix cores."""
+
+    def __init__(self, A: torch.Tensor, W: torch.Tensor, ckpt="store", accumulate: bool = False,
+                 stream=None):
+        super().__init__()
+        _need_cuda(A, W)
+        self.A, self.W = A, W
+        self.m, self.n = int(W.shape[0]), int(W.shape[1])
+        self.options = make_options(ckpt=ckpt, accumulate=accumulate)
+        sz = ctypes.c_size_t()
+        check(lib().pg_bdense_plan(ctypes.byref(self._plan), self.m, self.n, _ptr(A), _ptr(W),
+                                   _dtype_code(A), ctypes.byref(self.options), ctypes.byref(sz)),
+              "pg_bdense_plan")
+        self.workspace_bytes = sz.value
+        self._bind(A.device, stream)
+
+    def objective(self, X, stream=None):
+        _need_cuda(X)
+        return self._objective(X, (), stream)
+
+    def gradient(self, X, out=None, want_f=True, stream=None):
+        _need_cuda(X, out)
+        return self._gradient(X, (), out, want_f, stream)
+
+    def adjoint(self, X, fbar, out=None, stream=None):
+        _need_cuda(X, fbar, out)
+        return self._adjoint(X, fbar, out, stream)
+
+
+class MeshBatch(_Plan):
+    """Many meshes in one persistent launch; per-instance objectives."""
+
+    def __init__(self, inst, conn: torch.Tensor, B: torch.Tensor, w: torch.Tensor,
+                 ckpt="recompute", block: int = 0, tile: int = 0, accumulate: bool = False,
+                 stream=None):
+        super().__init__()
+        _need_cuda(conn, B, w)
+        self.conn, self.B, self.w = conn, B, w
+        rows = [tuple(int(v) for v in r) for r in inst]
+        self.n_inst = len(rows)
+        arr = (Instance * max(self.n_inst, 1))()
+        for i, (nn, ne, no, eo) in enumerate(rows):
+            arr[i] = Instance(nn, ne, no, eo)
+        self.n_nodes = max([r[0] + r[2] for r in rows], default=0)
+        k = conn.shape[1] if conn.dim() == 2 else 8
+        self.options = make_options("atomic", ckpt, block, tile, accumulate)
+        sz = ctypes.c_size_t()
+        check(lib().pg_mesh_batch_plan(ctypes.byref(self._plan), self.n_inst, arr, k, _ptr(conn),
+                                       _ptr(B), _ptr(w), _dtype_code(B), ctypes.byref(self.options),
+                                       ctypes.byref(sz)), "pg_mesh_batch_plan")
+        self.workspace_bytes = sz.value
+        self._bind(conn.device, stream)
+
+    def objective(self, x, stream=None):
+        _need_cuda(x)
+        return self._objective(x, (self.n_inst,), stream)
+
+    def gradient(self, x, out=None, want_f=True, stream=None):
+        _need_cuda(x, out)
+        return self._gradient(x, (self.n_inst,), out, want_f, stream)
+
+    def adjoint(self, x, fbar, out=None, stream=None):
+        _need_cuda(x, fbar, out)
+        return self._adjoint(x, fbar, out, stream)
+
+
+# ------------------------------------------------------------------ autograd
+
+class MeshFn(torch.autograd.Function):
+    """y = f(x) for a MeshObjective; backward seeds pg_adjoint with grad_output.
+
+    With ckpt='store' the forward keeps u_e in the plan's workspace and the
+    backward reads it; with 'recompute' the backward gathers x again."""
+
+    @staticmethod
+    def forward(ctx, x, obj: MeshObjective):
+        f = obj.objective(x.detach().contiguous())
+        ctx.obj = obj
+        ctx.save_for_backward(x)
+        return f
+
+    @staticmethod
+    def backward(ctx, gout):
+        (x,) = ctx.saved_tensors
+        fbar = gout.detach().to(torch.float64).contiguous().reshape(1)
+        g = ctx.obj.adjoint(x.detach().contiguous(), fbar)
+        return g, None
+
+
+class DenseFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, obj: DenseObjective):
+        ctx.obj = obj
+        ctx.save_for_backward(x)
+        return obj.objective(x.detach().contiguous())
+
+    @staticmethod
+    def backward(ctx, gout):
+        (x,) = ctx.saved_tensors
+        fbar = gout.detach().to(torch.float64).contiguous().reshape(1)
+        return ctx.obj.adjoint(x.detach().contiguous(), fbar), None
+
+
+class BatchedDenseFn(torch.autograd.Function):
+    """f(X) = sum W (.) psi(A X); forward GEMM with the psi epilogue (stores
+    V = W (.) psi'(A X) when ckpt='store'), backward GEMM A^T V."""
+
+    @staticmethod
+    def forward(ctx, X, obj: BatchedDense):
+        ctx.obj = obj
+        ctx.save_for_backward(X)
+        return obj.objective(X.detach().contiguous())
+
+    @staticmethod
+    def backward(ctx, gout):
+        (X,) = ctx.saved_tensors
+        fbar = gout.detach().to(torch.float64).contiguous().reshape(1)
+        return ctx.obj.adjoint(X.detach().contiguous(), fbar), None
+
+
+class MeshBatchFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, obj: MeshBatch):
+        ctx.obj = obj
+        ctx.save_for_backward(x)
+        return obj.objective(x.detach().contiguous())
+
+    @staticmethod
+    def backward(ctx, gout):
+        (x,) = ctx.saved_tensors
+        fbar = gout.detach().to(torch.float64).contiguous()
+        return ctx.obj.adjoint(x.detach().contiguous(), fbar), None

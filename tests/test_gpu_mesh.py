@@ -1,0 +1,198 @@
+"""Parity of the HIP mesh path (through the C ABI) with the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_13204_amd import inputs
+from _helpers import TOL_F32, TOL_F64_F, TOL_F64_G, mesh_to_dev, rel, srel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+VARIANTS = [("atomic", "recompute"), ("atomic", "store"), ("gather", "recompute"),
+            ("gather", "store")]
+
+
+def _obj(m, dtype="f64", **kw):
+    from paper_2507_13204_amd import MeshObjective
+    conn, B, w, x = mesh_to_dev(m, dtype)
+    return MeshObjective(conn, B, w, m.n_nodes, **kw), x
+
+
+def _oracle_grad(m, dtype="f64", fbar=1.0):
+    if dtype == "f32":
+        m = m.astype(np.float32)
+    return oracle.mesh_gradient(m.n_nodes, m.conn, m.B.astype(np.float64),
+                                m.w.astype(np.float64), m.x.astype(np.float64), fbar)
+
+
+def _check(m, f, g, dtype="f64", fbar=1.0, f_tol=None, g_tol=None):
+    f_ref, g_ref = _oracle_grad(m, dtype, fbar)
+    f_tol = f_tol or (TOL_F64_F if dtype == "f64" else TOL_F32)
+    g_tol = g_tol or (TOL_F64_G if dtype == "f64" else TOL_F32)
+    if f is not None:
+        assert srel(f, f_ref) <= f_tol, (f, f_ref)
+    assert rel(g, g_ref) <= g_tol, rel(g, g_ref)
+
+
+MESHES = {
+    "chain10k": lambda: inputs.chain(10_000),
+    "hex17": lambda: inputs.hex_mesh(17, seed=5),      # 4096 elements: 16 tiles of 256
+    "hex23": lambda: inputs.hex_mesh(23, seed=6),      # 10648 elements: ragged tail
+    "rand_k8": lambda: inputs.random_mesh(3000, 7001, 8, 7),
+    "rand_k4": lambda: inputs.random_mesh(500, 1333, 4, 8),
+    "rand_k5": lambda: inputs.random_mesh(700, 999, 5, 9),    # runtime-k kernel
+    "rand_k3": lambda: inputs.random_mesh(50, 77, 3, 10),
+}
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+@pytest.mark.parametrize("adj,ckpt", VARIANTS)
+def test_mesh_gradient_parity_f64(name, adj, ckpt):
+    m = MESHES[name]()
+    obj, x = _obj(m, "f64", adjoint=adj, ckpt=ckpt)
+    f, g = obj.gradient(x)
+    torch.cuda.synchronize()
+    _check(m, f.item(), g.cpu().numpy())
+    f2 = obj.objective(x).item()
+    assert srel(f2, oracle.mesh_objective(m.n_nodes, m.conn, m.B, m.w, m.x)) <= TOL_F64_F
+
+
+@pytest.mark.parametrize("tile", [1, 2, 4])
+@pytest.mark.parametrize("block", [64, 256, 1024])
+def test_mesh_launch_shapes(tile, block):
+    m = inputs.hex_mesh(19, seed=11)
+    obj, x = _obj(m, "f64", block=block, tile=tile)
+    f, g = obj.gradient(x)
+    _check(m, f.item(), g.cpu().numpy())
+
+
+@pytest.mark.parametrize("name", ["hex17", "rand_k8", "rand_k5", "chain10k"])
+@pytest.mark.parametrize("adj", ["atomic", "gather"])
+def test_mesh_gradient_parity_f32(name, adj):
+    m = MESHES[name]()
+    if name == "chain10k":
+        # psi'(u) cancels between neighbours (g_i = psi'(u_{i-1}) - psi'(u_i));
+        # compare with the oracle on the same FP32-rounded inputs
+        pass
+    obj, x = _obj(m, "f32", adjoint=adj)
+    f, g = obj.gradient(x)
+    assert g.dtype == torch.float32
+    _check(m, f.item(), g.cpu().numpy(), "f32")
+
+
+@pytest.mark.parametrize("adj,ckpt", VARIANTS)
+def test_adjoint_seed_and_tape(adj, ckpt):
+    m = inputs.hex_mesh(15, seed=12)
+    obj, x = _obj(m, "f64", adjoint=adj, ckpt=ckpt)
+    fbar = torch.tensor([-0.375], dtype=torch.float64, device="cuda")
+    if ckpt == "store":
+        from paper_2507_13204_amd.pgrad import PgError
+        with pytest.raises(PgError):
+            obj.adjoint(x, fbar)  # nothing stored yet
+        obj.objective(x)
+    g = obj.adjoint(x, fbar)
+    _check(m, None, g.cpu().numpy(), fbar=-0.375)
+
+
+def test_accumulate_adds_into_grad():
+    m = inputs.hex_mesh(13, seed=13)
+    for adj in ("atomic", "gather"):
+        obj, x = _obj(m, "f64", adjoint=adj, accumulate=True)
+        base = torch.linspace(-1, 1, m.n_nodes, dtype=torch.float64, device="cuda")
+        g = base.clone()
+        obj.gradient(x, out=g)
+        _, g_ref = _oracle_grad(m)
+        assert rel(g.cpu().numpy(), base.cpu().numpy() + g_ref) <= TOL_F64_G
+
+
+def test_gather_variant_is_bitwise_repeatable():
+    m = inputs.hex_mesh(31, seed=14)
+    obj, x = _obj(m, "f64", adjoint="gather")
+    outs = [obj.gradient(x) for _ in range(3)]
+    for f, g in outs[1:]:
+        assert f.item() == outs[0][0].item()
+        assert torch.equal(g, outs[0][1])
+    # the objective is reduced in a fixed order in every variant
+    obj2, _ = _obj(m, "f64", adjoint="atomic")
+    fs = [obj2.objective(x).item() for _ in range(3)]
+    assert fs[0] == fs[1] == fs[2]
+
+
+def test_hvp_parity():
+    m = inputs.hex_mesh(14, seed=15)
+    d = inputs.fd_directions((m.n_nodes,), 1, seed=16)[0]
+    obj, x = _obj(m, "f64")
+    h = obj.hvp(x, to_dev(d)).cpu().numpy()
+    ref = oracle.mesh_hvp(m.n_nodes, m.conn, m.B, m.w, m.x, d)
+    assert rel(h, ref) <= TOL_F64_G
+
+
+def test_degenerate_meshes():
+    from paper_2507_13204_amd import MeshObjective
+    # no elements: f = 0, grad = 0
+    conn = torch.zeros((0, 8), dtype=torch.int32, device="cuda")
+    B = torch.zeros((0, 8), dtype=torch.float64, device="cuda")
+    w = torch.zeros(0, dtype=torch.float64, device="cuda")
+    obj = MeshObjective(conn, B, w, 5)
+    x = torch.ones(5, dtype=torch.float64, device="cuda")
+    f, g = obj.gradient(x)
+    assert f.item() == 0.0 and not torch.any(g)
+    # one node, one element using it twice
+    m = inputs.Mesh(1, 1, 2, np.array([[0, 0]], np.int32), np.array([[1.0, 2.0]]),
+                    np.array([1.0]), np.array([0.5]))
+    for adj in ("atomic", "gather"):
+        o, xx = _obj(m, adjoint=adj)
+        f, g = o.gradient(xx)
+        _check(m, f.item(), g.cpu().numpy())
+    # x = 0 gives exactly zero
+    m = inputs.hex_mesh(6, seed=1)
+    o, xx = _obj(m)
+    f, g = o.gradient(torch.zeros_like(xx))
+    assert f.item() == 0.0 and not torch.any(g)
+
+
+def test_out_of_range_connectivity_is_rejected():
+    from paper_2507_13204_amd import MeshObjective
+    from paper_2507_13204_amd.pgrad import ERANGE, PgError
+    m = inputs.hex_mesh(5, seed=2)
+    bad = m.conn.copy()
+    bad[7, 3] = m.n_nodes
+    for adj in ("atomic", "gather"):
+        with pytest.raises(PgError) as ei:
+            MeshObjective(to_dev(bad), to_dev(m.B), to_dev(m.w), m.n_nodes, adjoint=adj)
+        assert ei.value.code == ERANGE
+
+
+def test_alias_is_rejected():
+    from paper_2507_13204_amd.pgrad import EALIAS, PgError
+    m = inputs.hex_mesh(6, seed=3)
+    obj, x = _obj(m)
+    with pytest.raises(PgError) as ei:
+        obj.gradient(x, out=x)
+    assert ei.value.code == EALIAS
+
+
+@pytest.mark.parametrize("n", [1, 2, 101, 1001, 10_000])
+def test_chain_sweep(n):
+    """The 1D chain over the sizes of the paper's sweep of dim(x)."""
+    m = inputs.chain(n)
+    obj, x = _obj(m)
+    f, g = obj.gradient(x)
+    _check(m, f.item(), g.cpu().numpy())
+
+
+def test_hex128_full_size_parity():
+    """128^3 nodes, 127^3 elements, in the launch configuration of the benchmark."""
+    m = inputs.hex_mesh(128)
+    for adj in ("atomic", "gather"):
+        obj, x = _obj(m, "f64", adjoint=adj)
+        f, g = obj.gradient(x)
+        _check(m, f.item(), g.cpu().numpy())
+        f_obj = obj.objective(x).item()
+        assert srel(f_obj, f.item()) <= 1e-14
+    # FP32 storage, FP64 accumulation
+    obj, x = _obj(m, "f32")
+    f, g = obj.gradient(x)
+    _check(m, f.item(), g.cpu().numpy(), "f32")
