@@ -67,6 +67,9 @@ struct pg_plan_s {
     // mesh / batch
     MeshView mesh;
     int64_t mesh_blocks_n = 0;
+    // colour classes: elements of colour c are elist[colour_off[c] .. colour_off[c+1])
+    std::vector<int64_t> colour_off;
+    size_t o_elist = NONE;
     // batch
     BatchView batch;
     std::vector<pg_instance> inst;
@@ -139,6 +142,8 @@ pg_plan_s* new_plan(Kind kind, pg_dtype dt, const pg_options& o) {
     return p;
 }
 
+constexpr int kMaxColours = 64;
+
 // ------------------------------------------------------------- mesh layout
 
 void layout_mesh(pg_plan_s* p) {
@@ -157,6 +162,12 @@ void layout_mesh(pg_plan_s* p) {
         p->o_cursor = L.take(sizeof(int32_t) * (size_t)m.n_nodes);
         p->o_inc = L.take(sizeof(int32_t) * (size_t)(m.n_elems * m.k));
         p->o_scan = L.take(sizeof(int64_t) * (size_t)scan_scratch_items(m.n_nodes));
+    }
+    if (p->opt.adjoint == PG_ADJ_COLOUR) {
+        // One extra partial slot per colour class (a class ends a workgroup early).
+        p->n_partials = (size_t)std::max<int64_t>(p->mesh_blocks_n, 1) + kMaxColours;
+        p->o_partials = L.take(sizeof(double) * p->n_partials);
+        p->o_elist = L.take(sizeof(int32_t) * (size_t)m.n_elems);
     }
     // FP32 gradients accumulate in an FP64 buffer before rounding once.
     if (p->dtype == PG_F32) p->o_gacc = L.take(sizeof(double) * (size_t)m.n_nodes);
@@ -343,6 +354,28 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
         if (!p->tape_valid) return fail(PG_ESTATE, "no stored forward values: call pg_objective first");
         q.u_in = p->at<double>(p->o_u);
     }
+    if (p->opt.adjoint == PG_ADJ_COLOUR) {
+        // Elements of one colour share no node: plain read-add-write, one
+        // pass per colour in a fixed order (deterministic).
+        q.gacc = f32 ? p->at<double>(p->o_gacc) : static_cast<double*>(grad);
+        if (f32 || !acc) PG_HIP(launch_zero(q.gacc, sizeof(double) * (size_t)m.n_nodes, s));
+        const int32_t* elist = p->at<int32_t>(p->o_elist);
+        int64_t slot = 0;
+        PG_HIP(tmark(p, 1, true, s));
+        for (size_t c = 0; c + 1 < p->colour_off.size(); ++c) {
+            q.elist = elist + p->colour_off[c];
+            q.elist_n = p->colour_off[c + 1] - p->colour_off[c];
+            q.partial_base = slot;
+            if (q.elist_n == 0) continue;
+            PG_HIP(launch_mesh_elem(m, obj ? M_GRAD_COLOUR : M_ADJ_COLOUR, q, s));
+            slot += mesh_blocks(q.elist_n, q.block, k_in_registers(m.k) ? q.ept : 1);
+        }
+        PG_HIP(tmark(p, 1, false, s));
+        if (f32)
+            PG_HIP(launch_f64_to_f32(q.gacc, static_cast<float*>(grad), m.n_nodes, acc, s));
+        if (obj && f_out) PG_HIP(launch_final_sum(q.partials, slot, f_out, s));
+        return PG_OK;
+    }
     if (p->opt.adjoint == PG_ADJ_GATHER) {
         q.v_out = p->at<double>(p->o_v);
         PG_HIP(tmark(p, 1, true, s));
@@ -368,6 +401,48 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
     return PG_OK;
 }
 
+// Greedy colouring in element order (plan time, on the host): element e
+// takes the smallest colour that no earlier element sharing one of its nodes
+// has.  Node masks record the colours already present at each node, so one
+// pass over conn suffices.  Then elements are listed colour by colour, in
+// ascending order inside a colour.
+pg_status mesh_colour(pg_plan p, hipStream_t s) {
+    const MeshView& m = p->mesh;
+    const int64_t items = m.n_elems * m.k;
+    std::vector<int32_t> conn((size_t)items);
+    if (items > 0) {
+        PG_HIP(hipMemcpyAsync(conn.data(), m.conn, sizeof(int32_t) * (size_t)items,
+                              hipMemcpyDeviceToHost, s));
+        PG_HIP(hipStreamSynchronize(s));
+    }
+    std::vector<uint64_t> node_mask((size_t)m.n_nodes, 0);
+    std::vector<int32_t> colour((size_t)m.n_elems);
+    int ncol = 0;
+    for (int64_t e = 0; e < m.n_elems; ++e) {
+        uint64_t used = 0;
+        for (int32_t j = 0; j < m.k; ++j) used |= node_mask[(size_t)conn[(size_t)(e * m.k + j)]];
+        if (~used == 0)
+            return fail(PG_EUNSUPPORTED, "element %lld needs more than %d colours", (long long)e,
+                        kMaxColours);
+        const int c = __builtin_ctzll(~used);
+        colour[(size_t)e] = c;
+        ncol = std::max(ncol, c + 1);
+        for (int32_t j = 0; j < m.k; ++j) node_mask[(size_t)conn[(size_t)(e * m.k + j)]] |= 1ull << c;
+    }
+    p->colour_off.assign((size_t)ncol + 1, 0);
+    for (int64_t e = 0; e < m.n_elems; ++e) p->colour_off[(size_t)colour[(size_t)e] + 1]++;
+    for (int c = 0; c < ncol; ++c) p->colour_off[(size_t)c + 1] += p->colour_off[(size_t)c];
+    std::vector<int32_t> elist((size_t)m.n_elems);
+    std::vector<int64_t> fill(p->colour_off.begin(), p->colour_off.end() - 1);
+    for (int64_t e = 0; e < m.n_elems; ++e) elist[(size_t)fill[(size_t)colour[(size_t)e]]++] = (int32_t)e;
+    if (m.n_elems > 0) {
+        PG_HIP(hipMemcpyAsync(p->at<int32_t>(p->o_elist), elist.data(),
+                              sizeof(int32_t) * (size_t)m.n_elems, hipMemcpyHostToDevice, s));
+        PG_HIP(hipStreamSynchronize(s));
+    }
+    return PG_OK;
+}
+
 pg_status mesh_bind(pg_plan p, hipStream_t s) {
     const MeshView& m = p->mesh;
     int32_t* flag = p->at<int32_t>(p->o_flag);
@@ -384,6 +459,10 @@ pg_status mesh_bind(pg_plan p, hipStream_t s) {
     PG_HIP(hipMemcpyAsync(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
     if (hflag) return fail(PG_ERANGE, "connectivity has an entry outside [0, %lld)", (long long)m.n_nodes);
+    if (p->opt.adjoint == PG_ADJ_COLOUR) {
+        pg_status cst = mesh_colour(p, s);
+        if (cst != PG_OK) return cst;
+    }
     if (p->opt.adjoint == PG_ADJ_GATHER) {
         int32_t* offs = p->at<int32_t>(p->o_offs);
         PG_HIP(launch_exclusive_scan(p->at<int32_t>(p->o_cursor), m.n_nodes, offs,
@@ -597,7 +676,6 @@ pg_status pg_mesh_plan(pg_plan* plan, int64_t n_nodes, int64_t n_elems, int32_t 
     if (st) return st;
     pg_options o;
     if ((st = check_opts(opts, &o))) return st;
-    if (o.adjoint == PG_ADJ_COLOUR) return fail(PG_EUNSUPPORTED, "colour adjoint is not available for mesh plans yet");
     if (n_nodes < 0 || n_elems < 0) return fail(PG_EINVAL, "n_nodes and n_elems must be >= 0");
     if (k < 1 || k > PG_MAX_K) return fail(PG_EINVAL, "k = %d outside [1, %d]", k, PG_MAX_K);
     if (n_nodes >= (1LL << 31) || n_elems * (int64_t)k >= (1LL << 31))

@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 VARIANTS = [("atomic", "recompute"), ("atomic", "store"), ("gather", "recompute"),
-            ("gather", "store")]
+            ("gather", "store"), ("colour", "recompute"), ("colour", "store")]
 
 
 def _obj(m, dtype="f64", **kw):
@@ -69,13 +69,9 @@ def test_mesh_launch_shapes(tile, block):
 
 
 @pytest.mark.parametrize("name", ["hex17", "rand_k8", "rand_k5", "chain10k"])
-@pytest.mark.parametrize("adj", ["atomic", "gather"])
+@pytest.mark.parametrize("adj", ["atomic", "gather", "colour"])
 def test_mesh_gradient_parity_f32(name, adj):
     m = MESHES[name]()
-    if name == "chain10k":
-        # psi'(u) cancels between neighbours (g_i = psi'(u_{i-1}) - psi'(u_i));
-        # compare with the oracle on the same FP32-rounded inputs
-        pass
     obj, x = _obj(m, "f32", adjoint=adj)
     f, g = obj.gradient(x)
     assert g.dtype == torch.float32
@@ -98,7 +94,7 @@ def test_adjoint_seed_and_tape(adj, ckpt):
 
 def test_accumulate_adds_into_grad():
     m = inputs.hex_mesh(13, seed=13)
-    for adj in ("atomic", "gather"):
+    for adj in ("atomic", "gather", "colour"):
         obj, x = _obj(m, "f64", adjoint=adj, accumulate=True)
         base = torch.linspace(-1, 1, m.n_nodes, dtype=torch.float64, device="cuda")
         g = base.clone()
@@ -107,9 +103,10 @@ def test_accumulate_adds_into_grad():
         assert rel(g.cpu().numpy(), base.cpu().numpy() + g_ref) <= TOL_F64_G
 
 
-def test_gather_variant_is_bitwise_repeatable():
+@pytest.mark.parametrize("adj", ["gather", "colour"])
+def test_deterministic_variants_are_bitwise_repeatable(adj):
     m = inputs.hex_mesh(31, seed=14)
-    obj, x = _obj(m, "f64", adjoint="gather")
+    obj, x = _obj(m, "f64", adjoint=adj)
     outs = [obj.gradient(x) for _ in range(3)]
     for f, g in outs[1:]:
         assert f.item() == outs[0][0].item()
@@ -142,7 +139,7 @@ def test_degenerate_meshes():
     # one node, one element using it twice
     m = inputs.Mesh(1, 1, 2, np.array([[0, 0]], np.int32), np.array([[1.0, 2.0]]),
                     np.array([1.0]), np.array([0.5]))
-    for adj in ("atomic", "gather"):
+    for adj in ("atomic", "gather", "colour"):
         o, xx = _obj(m, adjoint=adj)
         f, g = o.gradient(xx)
         _check(m, f.item(), g.cpu().numpy())
@@ -159,7 +156,7 @@ def test_out_of_range_connectivity_is_rejected():
     m = inputs.hex_mesh(5, seed=2)
     bad = m.conn.copy()
     bad[7, 3] = m.n_nodes
-    for adj in ("atomic", "gather"):
+    for adj in ("atomic", "gather", "colour"):
         with pytest.raises(PgError) as ei:
             MeshObjective(to_dev(bad), to_dev(m.B), to_dev(m.w), m.n_nodes, adjoint=adj)
         assert ei.value.code == ERANGE
@@ -186,7 +183,7 @@ def test_chain_sweep(n):
 def test_hex128_full_size_parity():
     """128^3 nodes, 127^3 elements, in the launch configuration of the benchmark."""
     m = inputs.hex_mesh(128)
-    for adj in ("atomic", "gather"):
+    for adj in ("atomic", "gather", "colour"):
         obj, x = _obj(m, "f64", adjoint=adj)
         f, g = obj.gradient(x)
         _check(m, f.item(), g.cpu().numpy())
