@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--copies", type=int, default=3, help="rotating input copies")
+    ap.add_argument("--scatter", type=int, default=0, help="0 combine in LDS, 1 direct atomics")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=6.0)
@@ -122,33 +123,38 @@ def main():
     for c in range(max(1, args.copies)):
         cc = (conn, B, w, x) if c == 0 else tuple(t.clone() for t in (conn, B, w, x))
         obj = MeshObjective(cc[0], cc[1], cc[2], m.n_nodes, adjoint=args.adjoint,
-                            block=args.block, tile=args.tile)
+                            block=args.block, tile=args.tile, scatter=args.scatter)
         copies.append((obj, cc[3], torch.empty_like(cc[3]),
                        torch.empty((), dtype=torch.float64, device=dev)))
     torch.cuda.synchronize()
 
+    def step(kind, i, rotate=True):
+        obj, xx, g, f = copies[i % len(copies) if rotate else 0]
+        if kind == "grad":
+            obj.gradient(xx, out=g)
+        else:
+            obj.objective(xx)
+
     def run(kind: str, steps: int, warmup: int, rotate: bool = True):
+        """ms per step over exactly `steps` back-to-back steps, then (in a
+        second, separately timed pass) the average duration of the dominant
+        kernel from the library's event hook."""
         for i in range(warmup):
-            obj, xx, g, f = copies[i % len(copies) if rotate else 0]
-            if kind == "grad":
-                obj.gradient(xx, out=g)
-            else:
-                obj.objective(xx)
-        for obj, *_ in copies:
-            obj.timing(1)
+            step(kind, i, rotate)
         torch.cuda.synchronize()
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         t0.record()
         for i in range(steps):
-            obj, xx, g, f = copies[i % len(copies) if rotate else 0]
-            if kind == "grad":
-                obj.gradient(xx, out=g)
-            else:
-                obj.objective(xx)
+            step(kind, i, rotate)
         t1.record()
         torch.cuda.synchronize()
         ms = t0.elapsed_time(t1) / steps
+        for obj, *_ in copies:
+            obj.timing(1)
+        for i in range(steps):
+            step(kind, i, rotate)
+        torch.cuda.synchronize()
         kms, kn = 0.0, 0
         for obj, *_ in copies:
             a, b = obj.timing_read()

@@ -95,6 +95,10 @@ typedef struct {
     int32_t accumulate; /* 0: gradients overwrite grad; 1: add into grad
                            (the shadow-argument convention of the generated
                            gradient in section 4) */
+    int32_t scatter;    /* atomic adjoint only: 0 = default (combine each
+                           workgroup's contributions per node in LDS, then one
+                           global atomic per node), 1 = one global atomic per
+                           contribution */
 } pg_options;
 
 /* One instance of a mesh batch: its nodes are x[node_off .. node_off+n_nodes)

@@ -36,6 +36,8 @@ struct Mfma<double> {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
     __device__ static double get(const acc_t& c, int r) { return c[r]; }
+    // Output row (within the 16 x 16 block) of register r in lanes 16*g .. 16*g+15.
+    __device__ static int row(int g, int r) { return g + 4 * r; }
 };
 
 template <>
@@ -46,6 +48,7 @@ struct Mfma<float> {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
     __device__ static double get(const acc_t& c, int r) { return (double)c[r]; }
+    __device__ static int row(int g, int r) { return 4 * g + r; }
 };
 
 // Elements of one operand tile each thread moves per k-step.
@@ -148,7 +151,10 @@ k_gemm_mfma(const T* __restrict__ A, const T* __restrict__ Bm, int64_t M, int64_
     }
 
     // Accumulator (x, y) register r of lane l holds C[row][col] with
-    // row = x*16 + 4*(l/16) + r and col = y*16 + l%16 inside the wave block.
+    // col = y*16 + l%16 and row = x*16 + MF::row(l/16, r) inside the wave
+    // block: the FP64 instruction interleaves rows across registers
+    // (l/16 + 4r), the FP32 one keeps them in consecutive registers
+    // (4(l/16) + r).
     double tsum = 0.0;
     const double fb = (EPI == EPI_BWD && fbar) ? fbar[0] : 1.0;
 #pragma unroll
@@ -157,7 +163,7 @@ k_gemm_mfma(const T* __restrict__ A, const T* __restrict__ Bm, int64_t M, int64_
         for (int y = 0; y < 4; ++y)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t gi = i0 + wm * 64 + x * 16 + 4 * lk + r;
+                const int64_t gi = i0 + wm * 64 + x * 16 + MF::row(lk, r);
                 const int64_t gj = j0 + wn * 64 + y * 16 + li;
                 if (gi < M && gj < N) {
                     const double c = MF::get(acc[x][y], r);

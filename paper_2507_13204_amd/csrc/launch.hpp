@@ -47,6 +47,7 @@ struct MeshPass {
     int64_t partial_base = 0;      // first partial slot of this launch
     int block = 256;
     int ept = 1;
+    int combine = 1;               // combine atomic contributions in LDS first
 };
 
 // Number of workgroups an element pass over n items launches.

@@ -14,6 +14,8 @@
 // either a hardware FP64 atomic add (the race case of section 3.3: the write
 // index is itself a view entry), a plain read-add-write inside one colour
 // class, or deferred to the node-parallel gather below.
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "launch.hpp"
 
@@ -99,11 +101,60 @@ __device__ __forceinline__ void load_b_row(const float* __restrict__ B, int64_t 
     }
 }
 
+// Workgroup-local combining of the atomic scatter.  FP64 atomics cost one
+// memory-side request per (instruction, cache line), whatever the number of
+// active lanes, so the workgroup first adds its contributions into an LDS
+// hash table keyed by node (open addressing, linear probing) and then issues
+// one global atomic per distinct node.  The hash keeps runs of consecutive
+// node numbers in consecutive slots, so the flush touches few cache lines
+// per instruction; a contribution that finds no slot within kMaxProbe steps
+// goes straight to global memory, so any connectivity is handled.
+constexpr int kAggSlots = 4096;
+constexpr int kMaxProbe = 64;
+
+struct AggTable {
+    int32_t key[kAggSlots];
+    double val[kAggSlots];
+};
+
+__device__ __forceinline__ uint32_t agg_hash(int32_t n) {
+    const uint32_t u = (uint32_t)n;
+    return (u + (u >> 12) * 2533u) & (kAggSlots - 1);
+}
+
+__device__ __forceinline__ void agg_clear(AggTable& t) {
+    for (int s = threadIdx.x; s < kAggSlots; s += blockDim.x) {
+        t.key[s] = -1;
+        t.val[s] = 0.0;
+    }
+}
+
+__device__ __forceinline__ void agg_add(AggTable& t, int32_t n, double c, double* g) {
+    uint32_t h = agg_hash(n);
+    for (int probe = 0; probe < kMaxProbe; ++probe) {
+        const int32_t old = atomicCAS(&t.key[h], -1, n);
+        if (old == -1 || old == n) {
+            atomicAdd(&t.val[h], c);
+            return;
+        }
+        h = (h + 1) & (kAggSlots - 1);
+    }
+    atomic_add_f64(g + n, c);
+}
+
+__device__ __forceinline__ void agg_flush(const AggTable& t, double* g) {
+    for (int s = threadIdx.x; s < kAggSlots; s += blockDim.x) {
+        const int32_t n = t.key[s];
+        if (n >= 0) atomic_add_f64(g + n, t.val[s]);
+    }
+}
+
 // Compile-time K: every row lives in registers.
-template <typename T, int K, int MODE, int EPT>
+template <typename T, int K, int MODE, int EPT, bool AGG>
 __global__ void __launch_bounds__(1024)
 k_mesh_elem(MeshView m, MeshPass p) {
     __shared__ double lds[16];
+    __shared__ typename std::conditional<AGG, AggTable, int>::type agg;
     const T* __restrict__ B = static_cast<const T*>(m.B);
     const T* __restrict__ W = static_cast<const T*>(m.w);
     const T* __restrict__ X = static_cast<const T*>(p.x);
@@ -188,7 +239,18 @@ k_mesh_elem(MeshView m, MeshPass p) {
         for (int i = 0; i < EPT; ++i)
             if (ok[i]) p.v_out[e[i]] = v[i];
     }
-    if constexpr (is_atomic(MODE)) {
+    if constexpr (is_atomic(MODE) && AGG) {
+        agg_clear(agg);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < EPT; ++i)
+            if (ok[i]) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) agg_add(agg, c[i][j], v[i] * to_f64(b[i][j]), p.gacc);
+            }
+        __syncthreads();
+        agg_flush(agg, p.gacc);
+    } else if constexpr (is_atomic(MODE)) {
 #pragma unroll
         for (int i = 0; i < EPT; ++i)
             if (ok[i]) {
@@ -470,7 +532,16 @@ hipError_t launch_elem_t(const MeshView& m, const MeshPass& p, hipStream_t s) {
     const int64_t n_items = p.elist ? p.elist_n : m.n_elems;
     const int64_t nb = mesh_blocks(n_items, p.block, EPT);
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_mesh_elem<T, K, MODE, EPT>), dim3((unsigned)nb), dim3(p.block), 0, s, m, p);
+    // Combine in LDS when the workgroup's contributions fill at most half the table.
+    // Combine in LDS when the workgroup's contributions fit the table twice over
+    // at worst (all distinct); meshes with locality fill it far less.
+    const bool agg = is_atomic(MODE) && p.combine && (int64_t)p.block * EPT * K <= 2 * kAggSlots;
+    if (agg)
+        hipLaunchKernelGGL((k_mesh_elem<T, K, MODE, EPT, true>), dim3((unsigned)nb), dim3(p.block), 0,
+                           s, m, p);
+    else
+        hipLaunchKernelGGL((k_mesh_elem<T, K, MODE, EPT, false>), dim3((unsigned)nb), dim3(p.block),
+                           0, s, m, p);
     return hipGetLastError();
 }
 
@@ -587,7 +658,7 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
     const uintptr_t a = reinterpret_cast<uintptr_t>(p);
     if ((a % 16) == 0 && (bytes % 16) == 0) {
         const int64_t n16 = (int64_t)(bytes / 16);
-        hipLaunchKernelGGL(k_zero16, dim3(stream_grid(n16, 256 * 4, 8192)), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_zero16, dim3(stream_grid(n16, 256, 1 << 20)), dim3(256), 0, s,
                            (uint4*)p, n16);
     } else {
         hipLaunchKernelGGL(k_zero1, dim3((unsigned)((bytes + 255) / 256)), dim3(256), 0, s,

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_default_options():
     o = P.lib().pg_default_options()
-    assert (o.adjoint, o.ckpt, o.block, o.tile, o.accumulate) == (0, 0, 0, 0, 0)
+    assert (o.adjoint, o.ckpt, o.block, o.tile, o.accumulate, o.scatter) == (0, 0, 0, 0, 0, 0)
 
 
 FAKE = 1 << 20  # an aligned non-null address; plan creation never dereferences it

@@ -193,3 +193,16 @@ def test_hex128_full_size_parity():
     obj, x = _obj(m, "f32")
     f, g = obj.gradient(x)
     _check(m, f.item(), g.cpu().numpy(), "f32")
+
+
+@pytest.mark.parametrize("name", ["hex23", "rand_k8", "rand_k4", "chain10k"])
+@pytest.mark.parametrize("scatter", [0, 1])
+@pytest.mark.parametrize("block,tile", [(256, 1), (128, 2), (64, 4), (512, 1)])
+def test_scatter_combining(name, scatter, block, tile):
+    """Atomic adjoint with and without the per-workgroup LDS combining."""
+    m = MESHES[name]()
+    obj, x = _obj(m, "f64", block=block, tile=tile, scatter=scatter)
+    f, g = obj.gradient(x)
+    _check(m, f.item(), g.cpu().numpy())
+    fbar = torch.tensor([1.75], dtype=torch.float64, device="cuda")
+    _check(m, None, obj.adjoint(x, fbar).cpu().numpy(), fbar=1.75)
