@@ -53,12 +53,15 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=6.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 512 MiB device copy (scale for byte counters)")
     return ap.parse_args()
 
 
 def traffic_record(kernel_key: str):
-    """HBM bytes per launch measured with rocprofv3 counters, if taken on the
-    current kernel source (else None)."""
+    """HBM bytes per launch of the dominant kernel, measured with rocprofv3
+    byte counters (profiles/traffic.json), or None if the kernel sources have
+    changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -68,11 +71,13 @@ def traffic_record(kernel_key: str):
         return None
     if not rec:
         return None
-    src = os.path.join(ROOT, rec.get("source", ""))
-    if not os.path.exists(src):
-        return None
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if digest != rec.get("source_sha256"):
+    h = hashlib.sha256()
+    for src in rec.get("sources", []):
+        p = os.path.join(ROOT, src)
+        if not os.path.exists(p):
+            return None
+        h.update(open(p, "rb").read())
+    if h.hexdigest() != rec.get("sources_sha256"):
         return None
     return rec.get("bytes_per_launch")
 
@@ -229,6 +234,14 @@ def main():
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(m, args.cpu_seconds, gbytes)
+
+    if args.calibrate_copy:
+        src = torch.empty(512 << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = src.numel()
 
     print(json.dumps(out), flush=True)
 

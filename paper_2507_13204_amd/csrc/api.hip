@@ -895,7 +895,9 @@ pg_status pg_timing(pg_plan p, int32_t mode) {
     if (mode < 0 || mode > 2) return fail(PG_EINVAL, "timing mode %d not in {0, 1, 2}", mode);
     if (mode != 0 && p->ev.empty()) {
         p->ev.resize(2 * kMaxTimed);
-        for (auto& e : p->ev) PG_HIP(hipEventCreate(&e));
+        // Timing-only events: no system-scope fence (cache writeback) at record,
+        // which would otherwise be counted in the kernel's time.
+        for (auto& e : p->ev) PG_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     }
     p->timing_mode = mode;
     p->ev_n = 0;
