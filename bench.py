@@ -53,6 +53,12 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=6.0)
+    ap.add_argument("--workload", default="hex", choices=["hex", "dense", "bdense", "batch", "chain"],
+                    help="hex (default, the headline), dense, bdense, batch, chain")
+    ap.add_argument("--dense-n", type=int, default=10_000)
+    ap.add_argument("--bd-m", type=int, default=4096)
+    ap.add_argument("--bd-n", type=int, default=1024)
+    ap.add_argument("--batch-n", type=int, default=256)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 512 MiB device copy (scale for byte counters)")
     return ap.parse_args()
@@ -100,21 +106,11 @@ def cpu_baseline(m, budget_s: float, gbytes: float):
             "cpu": platform.processor() or platform.machine()}
 
 
-def main():
-    args = parse()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
-        sys.exit(2)
-
+def bench_hex(args):
     import numpy as np
     import torch
     from paper_2507_13204_amd import MeshObjective, inputs
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
     dev = torch.device("cuda:0")
     tdt = torch.float64 if args.dtype == "f64" else torch.float32
     esz = 8 if args.dtype == "f64" else 4
@@ -244,6 +240,231 @@ def main():
         out["calibration_copy_bytes"] = src.numel()
 
     print(json.dumps(out), flush=True)
+
+
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def _hook_ms(plan, fn, steps):
+    import torch
+    plan.timing(1)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    ms, n = plan.timing_read()
+    plan.timing(0)
+    return ms / max(n, 1)
+
+
+def _line(metric, value, unit, args, ms, dtype, config, higher=True, **extra):
+    out = {"metric": metric, "value": round(value, 3), "unit": unit, "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+           "higher_is_better": higher, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic (seeded)", "config": config}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_dense(args):
+    """A 10,000 x 10,000 FP64 row reduction: f and its gradient in one pass over A."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2507_13204_amd import DenseObjective, inputs
+    n = args.dense_n
+    d = inputs.dense(n)
+    dev = torch.device("cuda:0")
+    tdt = torch.float64 if args.dtype == "f64" else torch.float32
+    esz = 8 if args.dtype == "f64" else 4
+    A = torch.from_numpy(d.A).to(dev, tdt)
+    w = torch.from_numpy(d.w).to(dev, tdt)
+    x = torch.from_numpy(d.x).to(dev, tdt)
+    obj = DenseObjective(A, w)
+    g = torch.empty_like(x)
+    ms_g = _timed(lambda: obj.gradient(x, out=g), args.steps, args.warmup)
+    ms_f = _timed(lambda: obj.objective(x), args.steps, args.warmup)
+    k_g = _hook_ms(obj, lambda: obj.gradient(x, out=g), args.steps)
+    gbytes = (n * n + 3 * n) * esz / 1e9
+    t0 = time.perf_counter()
+    oracle.dense_gradient(d.A, d.x, d.w)
+    cpu_s = time.perf_counter() - t0
+    _line("dense row-reduction gradient GB/s (A n x n, one pass over A)", gbytes / (ms_g * 1e-3),
+          "GB/s", args, ms_g, args.dtype,
+          {"workload": f"dense {n}x{n} {args.dtype}, one workgroup team per row band"},
+          gradient_over_objective=round(ms_g / ms_f, 4), objective_ms=round(ms_f, 5),
+          roofline={"bound": "hbm", "achieved": round(gbytes / (k_g * 1e-3), 2),
+                    "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(gbytes / (k_g * 1e-3) / PEAK_HBM_GBS, 4), "traffic": None,
+                    "kernel": "k_dense_fused", "kernel_ms": round(k_g, 5)},
+          cpu_baseline={"value": round(gbytes / cpu_s, 3), "unit": "GB/s", "cores": 1,
+                        "kind": "oracle", "sample": f"one Dot2 FP64 gradient, {n}x{n}"})
+
+
+def bench_bdense(args):
+    """A 4096^2, X 4096 x 1024: forward product with the psi epilogue and the
+    backward product A^T V on the matrix cores."""
+    import numpy as np
+    import torch
+    from paper_2507_13204_amd import BatchedDense, inputs
+    m, n = args.bd_m, args.bd_n
+    b = inputs.batched_dense(m, n)
+    dev = torch.device("cuda:0")
+    tdt = torch.float64 if args.dtype == "f64" else torch.float32
+    A = torch.from_numpy(b.A).to(dev, tdt)
+    W = torch.from_numpy(b.W).to(dev, tdt)
+    X = torch.from_numpy(b.X).to(dev, tdt)
+    res = {}
+    for ckpt in ("store", "recompute"):
+        obj = BatchedDense(A, W, ckpt=ckpt)
+        G = torch.empty_like(X)
+        fbar = torch.ones(1, dtype=torch.float64, device=dev)
+        ms_f = _timed(lambda: obj.objective(X), args.steps, args.warmup)
+        ms_b = _timed(lambda: obj.adjoint(X, fbar, out=G), args.steps, args.warmup)
+        ms_g = _timed(lambda: obj.gradient(X, out=G), args.steps, args.warmup)
+        k_f = _hook_ms(obj, lambda: obj.objective(X), args.steps)
+        res[ckpt] = {"objective_ms": round(ms_f, 4), "adjoint_ms": round(ms_b, 4),
+                     "gradient_ms": round(ms_g, 4), "fwd_kernel_ms": round(k_f, 4),
+                     "fwd_plus_bwd_over_fwd": round((ms_f + ms_b) / ms_f, 4)}
+        obj.close()
+    flop = 2.0 * m * m * n
+    peak = 78.6 if args.dtype == "f64" else 157.3
+    kf = res["store"]["fwd_kernel_ms"]
+    Xs = np.ascontiguousarray(b.X[:, :64])
+    t0 = time.perf_counter()
+    _ = b.A @ Xs
+    cpu_s = time.perf_counter() - t0
+    _line("batched dense gradient TFLOP/s (A m x m, X m x n, MFMA)",
+          2 * flop / (res["store"]["gradient_ms"] * 1e-3) / 1e12, "TFLOP/s", args,
+          res["store"]["gradient_ms"], args.dtype,
+          {"workload": f"batched dense A {m}x{m}, X {m}x{n}, {args.dtype} MFMA"},
+          variants=res,
+          roofline={"bound": "mfma", "achieved": round(flop / (kf * 1e-3) / 1e12, 3),
+                    "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(flop / (kf * 1e-3) / 1e12 / peak, 4), "traffic": None,
+                    "kernel": "k_gemm_mfma forward (psi epilogue)", "kernel_ms": kf},
+          cpu_baseline={"value": round(2 * m * m * 64 / cpu_s / 1e12, 5), "unit": "TFLOP/s",
+                        "cores": os.cpu_count(), "kind": "oracle",
+                        "sample": "the oracle's NumPy FP64 product A @ X on 64 columns"})
+
+
+def bench_batch(args):
+    """256 uneven hex meshes: one persistent launch (eager and HIP-graph replay)
+    against 256 per-instance gradient calls."""
+    import numpy as np
+    import torch
+    from paper_2507_13204_amd import MeshBatch, MeshObjective, inputs
+    from paper_2507_13204_amd import autotune
+    bt = inputs.uneven_batch(args.batch_n)
+    dev = torch.device("cuda:0")
+    conn = torch.from_numpy(bt.conn).to(dev)
+    B = torch.from_numpy(bt.B).to(dev)
+    w = torch.from_numpy(bt.w).to(dev)
+    x = torch.from_numpy(bt.x).to(dev)
+    N, E = int(bt.x.shape[0]), int(bt.conn.shape[0])
+    gbytes = (E * 8 * 4 + E * 8 * 8 + E * 8 + 2 * N * 8) / 1e9
+    tuned = autotune.tune_batch(bt.inst, conn, B, w, x, use_cache=False)
+    res = {"autotune": tuned}
+    g = torch.empty_like(x)
+    f = torch.empty(bt.n_inst, dtype=torch.float64, device=dev)
+    for ckpt in ("recompute", "store"):
+        ob = MeshBatch(bt.inst, conn, B, w, ckpt=ckpt, block=tuned["block"], tile=tuned["tile"])
+        ms_g = _timed(lambda: ob.gradient(x, out=g, f_out=f), args.steps, args.warmup)
+        fbar = torch.ones(bt.n_inst, dtype=torch.float64, device=dev)
+        ms_fb = _timed(lambda: (ob.objective(x, f_out=f), ob.adjoint(x, fbar, out=g)),
+                       args.steps, args.warmup)
+        res[ckpt] = {"gradient_ms": round(ms_g, 4), "objective_plus_adjoint_ms": round(ms_fb, 4)}
+        if ckpt == "recompute":
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(s):
+                ob.gradient(x, out=g, f_out=f, stream=s)
+                with torch.cuda.graph(graph, stream=s):
+                    ob.gradient(x, out=g, f_out=f, stream=s)
+            torch.cuda.current_stream().wait_stream(s)
+            ms_graph = _timed(graph.replay, args.steps, args.warmup)
+            res["graph_gradient_ms"] = round(ms_graph, 4)
+            k_ms = _hook_ms(ob, lambda: ob.gradient(x, out=g, f_out=f), args.steps)
+        ob.close()
+    # per-instance form: one plan per mesh, one gradient call each
+    plans = []
+    for i in range(bt.n_inst):
+        nn, ne, no, eo = (int(v) for v in bt.inst[i])
+        plans.append((MeshObjective(conn[eo:eo + ne], B[eo:eo + ne], w[eo:eo + ne], nn),
+                      x[no:no + nn], g[no:no + nn], f[i:i + 1].view(())))
+
+    def per_instance():
+        for p, xi, gi, fi in plans:
+            p.gradient(xi, out=gi, f_out=fi)
+
+    ms_pi = _timed(per_instance, max(3, args.steps // 10), 1)
+    res["per_instance_ms"] = round(ms_pi, 4)
+    best = min(res["recompute"]["gradient_ms"], res["graph_gradient_ms"])
+    _line("uneven batch gradient throughput (instances/s), 256 hex meshes in one launch",
+          bt.n_inst / (best * 1e-3), "instances/s", args, best, "f64",
+          {"workload": f"{bt.n_inst} hex meshes, sides log-uniform in [10,100], "
+                       f"{N} nodes, {E} elements"},
+          GBps=round(gbytes / (best * 1e-3), 2),
+          per_instance_instances_per_s=round(bt.n_inst / (ms_pi * 1e-3), 2),
+          batched_over_per_instance_speedup=round(ms_pi / best, 3),
+          variants=res,
+          roofline={"bound": "hbm", "achieved": round(gbytes / (k_ms * 1e-3), 2),
+                    "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(gbytes / (k_ms * 1e-3) / PEAK_HBM_GBS, 4), "traffic": None,
+                    "kernel": "k_batch_persistent", "kernel_ms": round(k_ms, 5)})
+
+
+def bench_chain(args):
+    """The 1D chain over the paper's sweep of dim(x) = 1, 100, ..., 10,000."""
+    import torch
+    from paper_2507_13204_amd import MeshObjective, inputs
+    dev = torch.device("cuda:0")
+    sweep = []
+    for n in [1] + list(range(100, 10001, 100)):
+        m = inputs.chain(n)
+        if m.n_elems == 0:
+            continue
+        obj = MeshObjective(torch.from_numpy(m.conn).to(dev), torch.from_numpy(m.B).to(dev),
+                            torch.from_numpy(m.w).to(dev), n)
+        x = torch.from_numpy(m.x).to(dev)
+        g = torch.empty_like(x)
+        f = torch.empty((), dtype=torch.float64, device=dev)
+        ms_g = _timed(lambda: obj.gradient(x, out=g, f_out=f), args.steps, args.warmup)
+        ms_f = _timed(lambda: obj.objective(x, f_out=f), args.steps, args.warmup)
+        sweep.append((n, round(ms_f * 1e3, 3), round(ms_g * 1e3, 3), round(ms_g / ms_f, 4)))
+        obj.close()
+    ratios = sorted(r[3] for r in sweep)
+    _line("1D chain gradient/objective wall-clock ratio (max over n = 100..10,000)", ratios[-1],
+          "ratio", args, sweep[-1][2] / 1e3, "f64",
+          {"workload": "1D chain, n = 100..10,000 (the paper's sweep of dim(x))"}, higher=False,
+          median_ratio=ratios[len(ratios) // 2], sweep_n_us_f_us_grad_ratio=sweep)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    {"hex": bench_hex, "dense": bench_dense, "bdense": bench_bdense, "batch": bench_batch,
+     "chain": bench_chain}[args.workload](args)
 
 
 if __name__ == "__main__":

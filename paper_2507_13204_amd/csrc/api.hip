@@ -10,7 +10,7 @@
 #include <numeric>
 #include <vector>
 
-#include "../../include/pgrad.h"
+#include "pgrad.h"
 #include "launch.hpp"
 
 using namespace pg;
@@ -74,7 +74,7 @@ struct pg_plan_s {
     BatchView batch;
     std::vector<pg_instance> inst;
     int64_t n_nodes_total = 0, n_elems_total = 0;
-    std::vector<int64_t> h_tile_inst, h_tile_first, h_tile_slot, h_node_off, h_elem_end, h_seg;
+    std::vector<int64_t> h_tiles, h_seg;
     int batch_grid = 0;
     // dense
     DenseView dense;
@@ -199,36 +199,30 @@ void layout_batch(pg_plan_s* p) {
     for (int32_t i = 0; i < ni; ++i)
         p->h_seg[i + 1] = p->h_seg[i] + (p->inst[i].n_elems + te - 1) / te;
     const int64_t nt = p->h_seg[ni];
-    p->h_tile_inst.clear();
-    p->h_tile_first.clear();
-    p->h_tile_slot.clear();
+    p->h_tiles.clear();
+    p->h_tiles.reserve((size_t)(4 * nt));
     for (int32_t oi : order) {
         const pg_instance& in = p->inst[oi];
         const int64_t tiles = (in.n_elems + te - 1) / te;
         for (int64_t t = 0; t < tiles; ++t) {
-            p->h_tile_inst.push_back(oi);
-            p->h_tile_first.push_back(in.elem_off + t * te);
-            p->h_tile_slot.push_back(p->h_seg[oi] + t);
+            const int64_t first = in.elem_off + t * te;
+            p->h_tiles.push_back(first);
+            p->h_tiles.push_back(std::min(first + te, in.elem_off + in.n_elems));
+            p->h_tiles.push_back(in.node_off);
+            p->h_tiles.push_back(((int64_t)oi << 40) | (p->h_seg[oi] + t));
         }
-    }
-    p->h_node_off.resize(ni);
-    p->h_elem_end.resize(ni);
-    for (int32_t i = 0; i < ni; ++i) {
-        p->h_node_off[i] = p->inst[i].node_off;
-        p->h_elem_end[i] = p->inst[i].elem_off + p->inst[i].n_elems;
     }
     p->batch.n_tiles = nt;
     p->n_partials = (size_t)std::max<int64_t>(nt, 1);
     p->o_partials = L.take(sizeof(double) * p->n_partials);
     p->o_flag = L.take(sizeof(int32_t) * 4);
-    // tables: tile_inst, tile_first, tile_slot (nt each), node_off, elem_end (ni), seg (ni+1)
-    p->o_tiles = L.take(sizeof(int64_t) * (size_t)(3 * nt + 3 * ni + 1));
+    // tables: tile records (4 x int64 each), then the instance segments (ni + 1)
+    p->o_tiles = L.take(sizeof(int64_t) * (size_t)(4 * nt + ni + 1));
     if (p->opt.ckpt == PG_STORE) p->o_u = L.take(sizeof(double) * (size_t)p->n_elems_total);
     if (p->dtype == PG_F32) p->o_gacc = L.take(sizeof(double) * (size_t)p->n_nodes_total);
     p->ws_bytes = L.total;
-    // 256 compute units; 8 resident workgroups of 256 threads per CU at most.
-    const int64_t cap = 256LL * std::max(1, 2048 / p->opt.block);
-    p->batch_grid = (int)std::max<int64_t>(1, std::min<int64_t>(nt, cap));
+    // The launcher sizes the persistent grid to the device's resident capacity.
+    p->batch_grid = 0;
 }
 
 // ------------------------------------------------------------ dense layout
@@ -498,12 +492,8 @@ pg_status batch_bind(pg_plan p, hipStream_t s) {
     // Upload the work list and instance tables.
     const int64_t nt = p->batch.n_tiles, ni = (int64_t)p->inst.size();
     std::vector<int64_t> tab;
-    tab.reserve((size_t)(3 * nt + 3 * ni + 1));
-    tab.insert(tab.end(), p->h_tile_inst.begin(), p->h_tile_inst.end());
-    tab.insert(tab.end(), p->h_tile_first.begin(), p->h_tile_first.end());
-    tab.insert(tab.end(), p->h_tile_slot.begin(), p->h_tile_slot.end());
-    tab.insert(tab.end(), p->h_node_off.begin(), p->h_node_off.end());
-    tab.insert(tab.end(), p->h_elem_end.begin(), p->h_elem_end.end());
+    tab.reserve((size_t)(4 * nt + ni + 1));
+    tab.insert(tab.end(), p->h_tiles.begin(), p->h_tiles.end());
     tab.insert(tab.end(), p->h_seg.begin(), p->h_seg.end());
     int64_t* dtab = p->at<int64_t>(p->o_tiles);
     if (!tab.empty())
@@ -513,11 +503,7 @@ pg_status batch_bind(pg_plan p, hipStream_t s) {
     PG_HIP(hipMemcpyAsync(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
     if (hflag) return fail(PG_ERANGE, "an instance's connectivity has an entry outside its node range");
-    p->batch.tile_inst = dtab;
-    p->batch.tile_first = dtab + nt;
-    p->batch.tile_slot = dtab + 2 * nt;
-    p->batch.inst_node_off = dtab + 3 * nt;
-    p->batch.inst_elem_end = dtab + 3 * nt + ni;
+    p->batch.tiles = dtab;
     return PG_OK;
 }
 
@@ -528,12 +514,13 @@ pg_status batch_run(pg_plan p, const void* x, const double* fbar, void* grad, do
     const bool obj = (want & W_OBJ) != 0;
     const bool grd = (want & W_GRAD) != 0;
     const int64_t ni = (int64_t)p->inst.size();
-    const int64_t* seg = p->at<int64_t>(p->o_tiles) + 3 * p->batch.n_tiles + 2 * ni;
+    const int64_t* seg = p->at<int64_t>(p->o_tiles) + 4 * p->batch.n_tiles;
     BatchPass q;
     q.x = x;
     q.partials = p->at<double>(p->o_partials);
     q.grid = p->batch_grid;
     q.block = p->opt.block;
+    q.combine = p->opt.scatter == 0;
     q.fbar = fbar;
     if (!grd) {
         q.u_store = p->at<double>(p->o_u);
@@ -721,6 +708,7 @@ pg_status pg_mesh_batch_plan(pg_plan* plan, int32_t n_inst, const pg_instance* i
     if ((st = check_opts(opts, &o))) return st;
     if (o.adjoint != PG_ADJ_ATOMIC) return fail(PG_EUNSUPPORTED, "mesh batches use the atomic adjoint");
     if (n_inst < 0 || (n_inst > 0 && !inst)) return fail(PG_EINVAL, "bad instance table");
+    if (n_inst >= (1 << 23)) return fail(PG_EINVAL, "at most 2^23 - 1 instances per batch");
     if (k < 1 || k > PG_MAX_K) return fail(PG_EINVAL, "k = %d outside [1, %d]", k, PG_MAX_K);
     int64_t nn = 0, ne = 0;
     for (int32_t i = 0; i < n_inst; ++i) {

@@ -1,0 +1,278 @@
+// The element work shared by the single-mesh and the mesh-batch kernels:
+// row loads, the gather, psi / psi', and the reverse scatter (atomic combined
+// in LDS, colour read-add-write, or per-element adjoints for the
+// node-parallel gather).
+#pragma once
+
+#include <type_traits>
+
+#include "device_common.hpp"
+#include "launch.hpp"
+
+namespace pg {
+
+constexpr bool has_obj(int mode) {
+    return mode == M_PRIMAL || mode == M_GRAD_ATOMIC || mode == M_GRAD_V || mode == M_GRAD_COLOUR;
+}
+constexpr bool has_rev(int mode) { return mode != M_PRIMAL && mode != M_HVP; }
+constexpr bool is_atomic(int mode) { return mode == M_GRAD_ATOMIC || mode == M_ADJ_ATOMIC || mode == M_HVP; }
+constexpr bool is_colour(int mode) { return mode == M_GRAD_COLOUR || mode == M_ADJ_COLOUR; }
+constexpr bool writes_v(int mode) { return mode == M_GRAD_V || mode == M_ADJ_V; }
+
+template <typename T, int K>
+__device__ __forceinline__ void load_conn_row(const int32_t* __restrict__ conn, int64_t e,
+                                              int32_t (&c)[K]) {
+    if constexpr (K % 4 == 0) {
+        const int4* p = reinterpret_cast<const int4*>(conn + e * K);
+#pragma unroll
+        for (int q = 0; q < K / 4; ++q) {
+            int4 v = p[q];
+            c[4 * q] = v.x;
+            c[4 * q + 1] = v.y;
+            c[4 * q + 2] = v.z;
+            c[4 * q + 3] = v.w;
+        }
+    } else if constexpr (K % 2 == 0) {
+        const int2* p = reinterpret_cast<const int2*>(conn + e * K);
+#pragma unroll
+        for (int q = 0; q < K / 2; ++q) {
+            int2 v = p[q];
+            c[2 * q] = v.x;
+            c[2 * q + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) c[j] = conn[e * K + j];
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void load_b_row(const double* __restrict__ B, int64_t e,
+                                           double (&b)[K]) {
+    if constexpr (K % 2 == 0) {
+        const double2* p = reinterpret_cast<const double2*>(B + e * K);
+#pragma unroll
+        for (int q = 0; q < K / 2; ++q) {
+            double2 v = p[q];
+            b[2 * q] = v.x;
+            b[2 * q + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) b[j] = B[e * K + j];
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void load_b_row(const float* __restrict__ B, int64_t e, float (&b)[K]) {
+    if constexpr (K % 4 == 0) {
+        const float4* p = reinterpret_cast<const float4*>(B + e * K);
+#pragma unroll
+        for (int q = 0; q < K / 4; ++q) {
+            float4 v = p[q];
+            b[4 * q] = v.x;
+            b[4 * q + 1] = v.y;
+            b[4 * q + 2] = v.z;
+            b[4 * q + 3] = v.w;
+        }
+    } else if constexpr (K % 2 == 0) {
+        const float2* p = reinterpret_cast<const float2*>(B + e * K);
+#pragma unroll
+        for (int q = 0; q < K / 2; ++q) {
+            float2 v = p[q];
+            b[2 * q] = v.x;
+            b[2 * q + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) b[j] = B[e * K + j];
+    }
+}
+
+// Workgroup-local combining of the atomic scatter.  FP64 atomics cost one
+// memory-side request per (instruction, cache line), whatever the number of
+// active lanes, so the workgroup first adds its contributions into an LDS
+// hash table keyed by node (open addressing, linear probing) and then issues
+// one global atomic per distinct node.  The hash keeps runs of consecutive
+// node numbers in consecutive slots, so the flush touches few cache lines
+// per instruction; a contribution that finds no slot within kMaxProbe steps
+// goes straight to global memory, so any connectivity is handled.
+constexpr int kAggSlots = 4096;
+constexpr int kMaxProbe = 64;
+
+struct AggTable {
+    int32_t key[kAggSlots];
+    double val[kAggSlots];
+};
+
+__device__ __forceinline__ uint32_t agg_hash(int32_t n) {
+    const uint32_t u = (uint32_t)n;
+    return (u + (u >> 12) * 2533u) & (kAggSlots - 1);
+}
+
+__device__ __forceinline__ void agg_clear(AggTable& t) {
+    for (int s = threadIdx.x; s < kAggSlots; s += blockDim.x) {
+        t.key[s] = -1;
+        t.val[s] = 0.0;
+    }
+}
+
+__device__ __forceinline__ void agg_add(AggTable& t, int32_t n, double c, double* g) {
+    uint32_t h = agg_hash(n);
+    for (int probe = 0; probe < kMaxProbe; ++probe) {
+        const int32_t old = atomicCAS(&t.key[h], -1, n);
+        if (old == -1 || old == n) {
+            atomicAdd(&t.val[h], c);
+            return;
+        }
+        h = (h + 1) & (kAggSlots - 1);
+    }
+    atomic_add_f64(g + n, c);
+}
+
+__device__ __forceinline__ void agg_flush(const AggTable& t, double* g) {
+    for (int s = threadIdx.x; s < kAggSlots; s += blockDim.x) {
+        const int32_t n = t.key[s];
+        if (n >= 0) atomic_add_f64(g + n, t.val[s]);
+    }
+}
+
+
+// Arguments of one element tile (device pointers; element-indexed arrays are
+// indexed by the element number e, node arrays by noff + conn[e, j]).
+struct TileArgs {
+    const int32_t* conn;
+    const void* B;
+    const void* w;
+    const void* x;
+    const void* xd;        // M_HVP direction
+    const double* u_in;    // stored forward values (replace the gather)
+    double* u_store;       // store forward values here
+    double* v_out;         // per-element adjoints (M_*_V)
+    double* gacc;          // FP64 accumulation target (atomic / colour modes)
+    const int32_t* elist;  // element list (item -> element); nullptr: identity
+};
+
+// The element work of one workgroup: items first + i*blockDim + tid (i < EPT)
+// below `end`.  Loads for all owned elements are issued before any
+// arithmetic; with AGG the atomic scatter is combined in `tab` (every thread
+// of the workgroup must call this).  Returns this thread's sum of the
+// objective terms w_e psi(u_e) (0 when the mode has no objective).
+template <typename T, int K, int MODE, int EPT, bool AGG>
+__device__ __forceinline__ double elem_tile(const TileArgs& a, int64_t first, int64_t end,
+                                            int64_t noff, double fb, AggTable* tab) {
+    const T* __restrict__ B = static_cast<const T*>(a.B);
+    const T* __restrict__ W = static_cast<const T*>(a.w);
+    const T* __restrict__ X = static_cast<const T*>(a.x) + noff;
+    const T* __restrict__ XD = static_cast<const T*>(a.xd);
+    const int32_t* __restrict__ conn = a.conn;
+    const int bs = blockDim.x;
+    int64_t e[EPT];
+    bool ok[EPT];
+    int32_t c[EPT][K];
+    T b[EPT][K];
+    T wv[EPT];
+    double u[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int64_t idx = first + (int64_t)i * bs + threadIdx.x;
+        ok[i] = idx < end;
+        e[i] = ok[i] ? (a.elist ? (int64_t)a.elist[idx] : idx) : 0;
+    }
+    // Phase 1: rows of conn, B and w for every owned element.
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        if (ok[i]) {
+            load_conn_row<T, K>(conn, e[i], c[i]);
+            load_b_row<K>(B, e[i], b[i]);
+            wv[i] = W[e[i]];
+        }
+    }
+    // Phase 2: the gather (or the stored forward value).
+    if (a.u_in) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) u[i] = ok[i] ? a.u_in[e[i]] : 0.0;
+    } else {
+        T xv[EPT][K];
+#pragma unroll
+        for (int i = 0; i < EPT; ++i)
+            if (ok[i]) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) xv[i][j] = X[c[i][j]];
+            }
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            double acc = 0.0;
+            if (ok[i]) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) acc += to_f64(b[i][j]) * to_f64(xv[i][j]);
+            }
+            u[i] = acc;
+        }
+        if (a.u_store) {
+#pragma unroll
+            for (int i = 0; i < EPT; ++i)
+                if (ok[i]) a.u_store[e[i]] = u[i];
+        }
+    }
+    // Phase 3: nonlinearity, objective terms and local adjoints.
+    double tsum = 0.0;
+    double v[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const double s = u[i], s2 = s * s;
+        const double wd = ok[i] ? to_f64(wv[i]) : 0.0;
+        if constexpr (has_obj(MODE)) tsum += wd * psi_from_sq(s2);
+        if constexpr (has_rev(MODE)) v[i] = fb * wd * dpsi_from(s, s2);
+        if constexpr (MODE == M_HVP) {
+            double q = 0.0;
+            if (ok[i]) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) q += to_f64(b[i][j]) * to_f64(XD[noff + c[i][j]]);
+            }
+            v[i] = wd * ddpsi_from_sq(s2) * q;
+        }
+    }
+    // Phase 4: the reverse scatter.
+    double* __restrict__ G = a.gacc ? a.gacc + noff : nullptr;
+    if constexpr (writes_v(MODE)) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i)
+            if (ok[i]) a.v_out[e[i]] = v[i];
+    }
+    if constexpr (is_atomic(MODE) && AGG) {
+        agg_clear(*tab);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < EPT; ++i)
+            if (ok[i]) {
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+                    agg_add(*tab, (int32_t)(noff + c[i][j]), v[i] * to_f64(b[i][j]), a.gacc);
+            }
+        __syncthreads();
+        agg_flush(*tab, a.gacc);
+        __syncthreads();
+    } else if constexpr (is_atomic(MODE)) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i)
+            if (ok[i]) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) atomic_add_f64(G + c[i][j], v[i] * to_f64(b[i][j]));
+            }
+    }
+    if constexpr (is_colour(MODE)) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i)
+            if (ok[i]) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    double* g = G + c[i][j];
+                    *g = *g + v[i] * to_f64(b[i][j]);
+                }
+            }
+    }
+    return tsum;
+}
+
+}  // namespace pg

@@ -98,12 +98,11 @@ struct BatchView {
     const int32_t* conn = nullptr;
     const void* B = nullptr;
     const void* w = nullptr;
-    // device tables
-    const int64_t* tile_inst = nullptr;   // instance of each tile (work-list order)
-    const int64_t* tile_first = nullptr;  // first global element of each tile
-    const int64_t* tile_slot = nullptr;   // partial slot of each tile (instance-major)
-    const int64_t* inst_node_off = nullptr;
-    const int64_t* inst_elem_end = nullptr;  // one past the last element of the instance
+    // Work list, one 32-byte record per tile in processing order:
+    // {first element, one past the last element, node offset of the instance,
+    //  (instance << 40) | partial slot}.  Slots are laid out instance by
+    // instance, so the segmented reduction sums each instance in order.
+    const int64_t* tiles = nullptr;
     int64_t n_tiles = 0;
     int tile_elems = 0;                   // elements per tile
 };
@@ -117,8 +116,9 @@ struct BatchPass {
     double* partials = nullptr;    // one slot per tile
     const double* u_in = nullptr;
     double* u_store = nullptr;
-    int grid = 0;                  // persistent workgroups
+    int grid = 0;                  // cap on persistent workgroups (0: device capacity)
     int block = 256;
+    int combine = 1;               // combine atomic contributions per tile in LDS
 };
 
 hipError_t launch_batch_persistent(const BatchView& b, BatchMode mode, const BatchPass& p,

@@ -16,138 +16,11 @@
 // class, or deferred to the node-parallel gather below.
 #include <type_traits>
 
-#include "device_common.hpp"
-#include "launch.hpp"
+#include "elem_tile.hpp"
 
 namespace pg {
 
 namespace {
-
-constexpr bool has_obj(int mode) {
-    return mode == M_PRIMAL || mode == M_GRAD_ATOMIC || mode == M_GRAD_V || mode == M_GRAD_COLOUR;
-}
-constexpr bool has_rev(int mode) { return mode != M_PRIMAL && mode != M_HVP; }
-constexpr bool is_atomic(int mode) { return mode == M_GRAD_ATOMIC || mode == M_ADJ_ATOMIC || mode == M_HVP; }
-constexpr bool is_colour(int mode) { return mode == M_GRAD_COLOUR || mode == M_ADJ_COLOUR; }
-constexpr bool writes_v(int mode) { return mode == M_GRAD_V || mode == M_ADJ_V; }
-
-template <typename T, int K>
-__device__ __forceinline__ void load_conn_row(const int32_t* __restrict__ conn, int64_t e,
-                                              int32_t (&c)[K]) {
-    if constexpr (K % 4 == 0) {
-        const int4* p = reinterpret_cast<const int4*>(conn + e * K);
-#pragma unroll
-        for (int q = 0; q < K / 4; ++q) {
-            int4 v = p[q];
-            c[4 * q] = v.x;
-            c[4 * q + 1] = v.y;
-            c[4 * q + 2] = v.z;
-            c[4 * q + 3] = v.w;
-        }
-    } else if constexpr (K % 2 == 0) {
-        const int2* p = reinterpret_cast<const int2*>(conn + e * K);
-#pragma unroll
-        for (int q = 0; q < K / 2; ++q) {
-            int2 v = p[q];
-            c[2 * q] = v.x;
-            c[2 * q + 1] = v.y;
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < K; ++j) c[j] = conn[e * K + j];
-    }
-}
-
-template <int K>
-__device__ __forceinline__ void load_b_row(const double* __restrict__ B, int64_t e,
-                                           double (&b)[K]) {
-    if constexpr (K % 2 == 0) {
-        const double2* p = reinterpret_cast<const double2*>(B + e * K);
-#pragma unroll
-        for (int q = 0; q < K / 2; ++q) {
-            double2 v = p[q];
-            b[2 * q] = v.x;
-            b[2 * q + 1] = v.y;
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < K; ++j) b[j] = B[e * K + j];
-    }
-}
-
-template <int K>
-__device__ __forceinline__ void load_b_row(const float* __restrict__ B, int64_t e, float (&b)[K]) {
-    if constexpr (K % 4 == 0) {
-        const float4* p = reinterpret_cast<const float4*>(B + e * K);
-#pragma unroll
-        for (int q = 0; q < K / 4; ++q) {
-            float4 v = p[q];
-            b[4 * q] = v.x;
-            b[4 * q + 1] = v.y;
-            b[4 * q + 2] = v.z;
-            b[4 * q + 3] = v.w;
-        }
-    } else if constexpr (K % 2 == 0) {
-        const float2* p = reinterpret_cast<const float2*>(B + e * K);
-#pragma unroll
-        for (int q = 0; q < K / 2; ++q) {
-            float2 v = p[q];
-            b[2 * q] = v.x;
-            b[2 * q + 1] = v.y;
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < K; ++j) b[j] = B[e * K + j];
-    }
-}
-
-// Workgroup-local combining of the atomic scatter.  FP64 atomics cost one
-// memory-side request per (instruction, cache line), whatever the number of
-// active lanes, so the workgroup first adds its contributions into an LDS
-// hash table keyed by node (open addressing, linear probing) and then issues
-// one global atomic per distinct node.  The hash keeps runs of consecutive
-// node numbers in consecutive slots, so the flush touches few cache lines
-// per instruction; a contribution that finds no slot within kMaxProbe steps
-// goes straight to global memory, so any connectivity is handled.
-constexpr int kAggSlots = 4096;
-constexpr int kMaxProbe = 64;
-
-struct AggTable {
-    int32_t key[kAggSlots];
-    double val[kAggSlots];
-};
-
-__device__ __forceinline__ uint32_t agg_hash(int32_t n) {
-    const uint32_t u = (uint32_t)n;
-    return (u + (u >> 12) * 2533u) & (kAggSlots - 1);
-}
-
-__device__ __forceinline__ void agg_clear(AggTable& t) {
-    for (int s = threadIdx.x; s < kAggSlots; s += blockDim.x) {
-        t.key[s] = -1;
-        t.val[s] = 0.0;
-    }
-}
-
-__device__ __forceinline__ void agg_add(AggTable& t, int32_t n, double c, double* g) {
-    uint32_t h = agg_hash(n);
-    for (int probe = 0; probe < kMaxProbe; ++probe) {
-        const int32_t old = atomicCAS(&t.key[h], -1, n);
-        if (old == -1 || old == n) {
-            atomicAdd(&t.val[h], c);
-            return;
-        }
-        h = (h + 1) & (kAggSlots - 1);
-    }
-    atomic_add_f64(g + n, c);
-}
-
-__device__ __forceinline__ void agg_flush(const AggTable& t, double* g) {
-    for (int s = threadIdx.x; s < kAggSlots; s += blockDim.x) {
-        const int32_t n = t.key[s];
-        if (n >= 0) atomic_add_f64(g + n, t.val[s]);
-    }
-}
 
 // Compile-time K: every row lives in registers.
 template <typename T, int K, int MODE, int EPT, bool AGG>
@@ -155,120 +28,15 @@ __global__ void __launch_bounds__(1024)
 k_mesh_elem(MeshView m, MeshPass p) {
     __shared__ double lds[16];
     __shared__ typename std::conditional<AGG, AggTable, int>::type agg;
-    const T* __restrict__ B = static_cast<const T*>(m.B);
-    const T* __restrict__ W = static_cast<const T*>(m.w);
-    const T* __restrict__ X = static_cast<const T*>(p.x);
-    const T* __restrict__ XD = static_cast<const T*>(p.xd);
-    const int32_t* __restrict__ conn = m.conn;
     const int64_t n_items = p.elist ? p.elist_n : m.n_elems;
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
-    const int bs = blockDim.x;
-    const int64_t base = (int64_t)lb * bs * EPT + threadIdx.x;
     double fb = 1.0;
     if constexpr (has_rev(MODE)) fb = p.fbar ? p.fbar[0] : 1.0;
-
-    int64_t e[EPT];
-    bool ok[EPT];
-    int32_t c[EPT][K];
-    T b[EPT][K];
-    T wv[EPT];
-    double u[EPT];
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int64_t idx = base + (int64_t)i * bs;
-        ok[i] = idx < n_items;
-        e[i] = ok[i] ? (p.elist ? (int64_t)p.elist[idx] : idx) : 0;
-    }
-    // Phase 1: rows of conn, B and w for every owned element.
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        if (ok[i]) {
-            load_conn_row<T, K>(conn, e[i], c[i]);
-            load_b_row<K>(B, e[i], b[i]);
-            wv[i] = W[e[i]];
-        }
-    }
-    // Phase 2: the gather (or the stored forward value).
-    if (p.u_in) {
-#pragma unroll
-        for (int i = 0; i < EPT; ++i) u[i] = ok[i] ? p.u_in[e[i]] : 0.0;
-    } else {
-        T xv[EPT][K];
-#pragma unroll
-        for (int i = 0; i < EPT; ++i)
-            if (ok[i]) {
-#pragma unroll
-                for (int j = 0; j < K; ++j) xv[i][j] = X[c[i][j]];
-            }
-#pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            double acc = 0.0;
-            if (ok[i]) {
-#pragma unroll
-                for (int j = 0; j < K; ++j) acc += to_f64(b[i][j]) * to_f64(xv[i][j]);
-            }
-            u[i] = acc;
-        }
-        if (p.u_store) {
-#pragma unroll
-            for (int i = 0; i < EPT; ++i)
-                if (ok[i]) p.u_store[e[i]] = u[i];
-        }
-    }
-    // Phase 3: nonlinearity, objective terms and local adjoints.
-    double tsum = 0.0;
-    double v[EPT];
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const double s = u[i], s2 = s * s;
-        const double wd = ok[i] ? to_f64(wv[i]) : 0.0;
-        if constexpr (has_obj(MODE)) tsum += wd * psi_from_sq(s2);
-        if constexpr (has_rev(MODE)) v[i] = fb * wd * dpsi_from(s, s2);
-        if constexpr (MODE == M_HVP) {
-            double q = 0.0;
-            if (ok[i]) {
-#pragma unroll
-                for (int j = 0; j < K; ++j) q += to_f64(b[i][j]) * to_f64(XD[c[i][j]]);
-            }
-            v[i] = wd * ddpsi_from_sq(s2) * q;
-        }
-    }
-    // Phase 4: the reverse scatter.
-    if constexpr (writes_v(MODE)) {
-#pragma unroll
-        for (int i = 0; i < EPT; ++i)
-            if (ok[i]) p.v_out[e[i]] = v[i];
-    }
-    if constexpr (is_atomic(MODE) && AGG) {
-        agg_clear(agg);
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < EPT; ++i)
-            if (ok[i]) {
-#pragma unroll
-                for (int j = 0; j < K; ++j) agg_add(agg, c[i][j], v[i] * to_f64(b[i][j]), p.gacc);
-            }
-        __syncthreads();
-        agg_flush(agg, p.gacc);
-    } else if constexpr (is_atomic(MODE)) {
-#pragma unroll
-        for (int i = 0; i < EPT; ++i)
-            if (ok[i]) {
-#pragma unroll
-                for (int j = 0; j < K; ++j) atomic_add_f64(p.gacc + c[i][j], v[i] * to_f64(b[i][j]));
-            }
-    }
-    if constexpr (is_colour(MODE)) {
-#pragma unroll
-        for (int i = 0; i < EPT; ++i)
-            if (ok[i]) {
-#pragma unroll
-                for (int j = 0; j < K; ++j) {
-                    double* g = p.gacc + c[i][j];
-                    *g = *g + v[i] * to_f64(b[i][j]);
-                }
-            }
-    }
+    TileArgs a{m.conn, m.B, m.w, p.x, p.xd, p.u_in, p.u_store, p.v_out, p.gacc, p.elist};
+    AggTable* tab = nullptr;
+    if constexpr (AGG) tab = &agg;
+    const double tsum = elem_tile<T, K, MODE, EPT, AGG>(a, (int64_t)lb * blockDim.x * EPT, n_items,
+                                                        0, fb, tab);
     if constexpr (has_obj(MODE)) {
         const double s = block_sum_dyn(tsum, lds);
         if (threadIdx.x == 0) p.partials[p.partial_base + lb] = s;

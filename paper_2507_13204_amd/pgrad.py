@@ -183,14 +183,16 @@ class _Plan:
         return ms.value, n.value
 
     # generic calls -----------------------------------------------------
-    def _objective(self, x, f_shape, stream=None):
-        f = torch.empty(f_shape, dtype=torch.float64, device=x.device)
+    def _objective(self, x, f_shape, stream=None, f_out=None):
+        f = torch.empty(f_shape, dtype=torch.float64, device=x.device) if f_out is None else f_out
         check(lib().pg_objective(self._plan, _ptr(x), _ptr(f), _stream(stream)), "pg_objective")
         return f
 
-    def _gradient(self, x, f_shape, out=None, want_f=True, stream=None):
+    def _gradient(self, x, f_shape, out=None, want_f=True, stream=None, f_out=None):
         g = torch.empty_like(x) if out is None else out
-        f = torch.empty(f_shape, dtype=torch.float64, device=x.device) if want_f else None
+        f = f_out
+        if f is None and want_f:
+            f = torch.empty(f_shape, dtype=torch.float64, device=x.device)
         check(lib().pg_gradient(self._plan, _ptr(x), _ptr(g), _ptr(f), _stream(stream)),
               "pg_gradient")
         return f, g
@@ -225,13 +227,13 @@ class MeshObjective(_Plan):
         self.workspace_bytes = sz.value
         self._bind(conn.device, stream)
 
-    def objective(self, x, stream=None):
+    def objective(self, x, stream=None, f_out=None):
         _need_cuda(x)
-        return self._objective(x, (), stream)
+        return self._objective(x, (), stream, f_out)
 
-    def gradient(self, x, out=None, want_f=True, stream=None):
+    def gradient(self, x, out=None, want_f=True, stream=None, f_out=None):
         _need_cuda(x, out)
-        return self._gradient(x, (), out, want_f, stream)
+        return self._gradient(x, (), out, want_f, stream, f_out)
 
     def adjoint(self, x, fbar, out=None, stream=None):
         _need_cuda(x, fbar, out)
@@ -260,13 +262,13 @@ class DenseObjective(_Plan):
         self.workspace_bytes = sz.value
         self._bind(A.device, stream)
 
-    def objective(self, x, stream=None):
+    def objective(self, x, stream=None, f_out=None):
         _need_cuda(x)
-        return self._objective(x, (), stream)
+        return self._objective(x, (), stream, f_out)
 
-    def gradient(self, x, out=None, want_f=True, stream=None):
+    def gradient(self, x, out=None, want_f=True, stream=None, f_out=None):
         _need_cuda(x, out)
-        return self._gradient(x, (), out, want_f, stream)
+        return self._gradient(x, (), out, want_f, stream, f_out)
 
     def adjoint(self, x, fbar, out=None, stream=None):
         _need_cuda(x, fbar, out)
@@ -290,13 +292,13 @@ class BatchedDense(_Plan):
         self.workspace_bytes = sz.value
         self._bind(A.device, stream)
 
-    def objective(self, X, stream=None):
+    def objective(self, X, stream=None, f_out=None):
         _need_cuda(X)
-        return self._objective(X, (), stream)
+        return self._objective(X, (), stream, f_out)
 
-    def gradient(self, X, out=None, want_f=True, stream=None):
+    def gradient(self, X, out=None, want_f=True, stream=None, f_out=None):
         _need_cuda(X, out)
-        return self._gradient(X, (), out, want_f, stream)
+        return self._gradient(X, (), out, want_f, stream, f_out)
 
     def adjoint(self, X, fbar, out=None, stream=None):
         _need_cuda(X, fbar, out)
@@ -308,7 +310,7 @@ class MeshBatch(_Plan):
 
     def __init__(self, inst, conn: torch.Tensor, B: torch.Tensor, w: torch.Tensor,
                  ckpt="recompute", block: int = 0, tile: int = 0, accumulate: bool = False,
-                 stream=None):
+                 scatter: int = 0, stream=None):
         super().__init__()
         _need_cuda(conn, B, w)
         self.conn, self.B, self.w = conn, B, w
@@ -319,7 +321,7 @@ class MeshBatch(_Plan):
             arr[i] = Instance(nn, ne, no, eo)
         self.n_nodes = max([r[0] + r[2] for r in rows], default=0)
         k = conn.shape[1] if conn.dim() == 2 else 8
-        self.options = make_options("atomic", ckpt, block, tile, accumulate)
+        self.options = make_options("atomic", ckpt, block, tile, accumulate, scatter)
         sz = ctypes.c_size_t()
         check(lib().pg_mesh_batch_plan(ctypes.byref(self._plan), self.n_inst, arr, k, _ptr(conn),
                                        _ptr(B), _ptr(w), _dtype_code(B), ctypes.byref(self.options),
@@ -327,13 +329,13 @@ class MeshBatch(_Plan):
         self.workspace_bytes = sz.value
         self._bind(conn.device, stream)
 
-    def objective(self, x, stream=None):
+    def objective(self, x, stream=None, f_out=None):
         _need_cuda(x)
-        return self._objective(x, (self.n_inst,), stream)
+        return self._objective(x, (self.n_inst,), stream, f_out)
 
-    def gradient(self, x, out=None, want_f=True, stream=None):
+    def gradient(self, x, out=None, want_f=True, stream=None, f_out=None):
         _need_cuda(x, out)
-        return self._gradient(x, (self.n_inst,), out, want_f, stream)
+        return self._gradient(x, (self.n_inst,), out, want_f, stream, f_out)
 
     def adjoint(self, x, fbar, out=None, stream=None):
         _need_cuda(x, fbar, out)

@@ -98,3 +98,23 @@ def test_batch_full_size_graph_replay():
         torch.cuda.synchronize()
         _check(bt, f.cpu().numpy(), g.cpu().numpy())
         assert rel(g.cpu().numpy(), g_e.cpu().numpy()) <= 1e-13
+
+
+@pytest.mark.parametrize("k", [2, 4, 5, 8])
+def test_batch_of_random_meshes(k):
+    """Instances with arbitrary connectivity (k = 5 takes the runtime-k kernel)."""
+    meshes = [inputs.random_mesh(nn, ne, k, 90 + i) for i, (nn, ne) in
+              enumerate([(40, 70), (7, 3), (300, 999), (1, 2), (64, 0), (500, 257)])]
+    inst, no, eo = [], 0, 0
+    for m in meshes:
+        inst.append((m.n_nodes, m.n_elems, no, eo))
+        no += m.n_nodes
+        eo += m.n_elems
+    bt = inputs.MeshBatch(np.array(inst, dtype=np.int64), k,
+                          np.concatenate([m.conn for m in meshes]),
+                          np.concatenate([m.B for m in meshes]),
+                          np.concatenate([m.w for m in meshes]),
+                          np.concatenate([m.x for m in meshes]), np.zeros(len(meshes)))
+    obj, x = _batch(bt, block=128)
+    f, g = obj.gradient(x)
+    _check(bt, f.cpu().numpy(), g.cpu().numpy())
