@@ -53,8 +53,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=6.0)
-    ap.add_argument("--workload", default="hex", choices=["hex", "dense", "bdense", "batch", "chain"],
-                    help="hex (default, the headline), dense, bdense, batch, chain")
+    ap.add_argument("--workload", default="hex",
+                    choices=["hex", "dense", "bdense", "batch", "chain", "paper"],
+                    help="hex (default, the headline), dense, bdense, batch, chain, paper")
     ap.add_argument("--dense-n", type=int, default=10_000)
     ap.add_argument("--bd-m", type=int, default=4096)
     ap.add_argument("--bd-n", type=int, default=1024)
@@ -452,6 +453,44 @@ def bench_chain(args):
           median_ratio=ratios[len(ratios) // 2], sweep_n_us_f_us_grad_ratio=sweep)
 
 
+# The paper's wall-clock times of f and of its generated gradient for dim(x) = 1
+# and 10,000 (figures of the results section), microseconds.
+PAPER_US = {"H100": {1: (41.79, 74.70), 10000: (47.82, 85.44)},
+            "MI250X (one GCD)": {1: (89.67, 194.68), 10000: (113.62, 233.82)},
+            "Ponte Vecchio": {1: (28.16, 56.07), 10000: (38.11, 68.24)}}
+
+
+def bench_paper(args):
+    """The paper's own example, f(x, b) = ||A(3x) - b||^2, swept over
+    dim(x) = 1, 100, ..., 10,000 as in its results section; gradient in x and b."""
+    import numpy as np
+    import torch
+    from paper_2507_13204_amd import Laplace1D
+    dev = torch.device("cuda:0")
+    res = {}
+    for adj in ("gather", "atomic"):
+        sweep = []
+        for n in [1] + list(range(100, 10001, 100)):
+            rng = np.random.default_rng(n)
+            x = torch.from_numpy(rng.uniform(-1, 1, n)).to(dev)
+            b = torch.from_numpy(rng.uniform(-1, 1, n)).to(dev)
+            lp = Laplace1D(n, adjoint=adj)
+            gx, gb = torch.empty_like(x), torch.empty_like(b)
+            f = torch.empty((), dtype=torch.float64, device=dev)
+            ms_g = _timed(lambda: lp.gradient(x, b, gx=gx, gb=gb, f_out=f), args.steps, args.warmup)
+            ms_f = _timed(lambda: lp.objective(x, b, f_out=f), args.steps, args.warmup)
+            sweep.append((n, round(ms_f * 1e3, 3), round(ms_g * 1e3, 3), round(ms_g / ms_f, 4)))
+            lp.close()
+        res[adj] = sweep
+    r = sorted(v[3] for v in res["gather"])
+    _line("paper example ||A(3x)-b||^2: gradient/objective wall-clock ratio, max over "
+          "dim(x) = 1..10,000", r[-1], "ratio", args, res["gather"][-1][2] / 1e3, "f64",
+          {"workload": "the paper's section 4 example, 1D Laplacian, dim(x) = 1, 100, ..., 10,000"},
+          higher=False, median_ratio=r[len(r) // 2],
+          atomic_schedule_max_ratio=max(v[3] for v in res["atomic"]),
+          paper_us_f_grad=PAPER_US, sweep_gather=res["gather"], sweep_atomic=res["atomic"])
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -464,7 +503,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     {"hex": bench_hex, "dense": bench_dense, "bdense": bench_bdense, "batch": bench_batch,
-     "chain": bench_chain}[args.workload](args)
+     "chain": bench_chain, "paper": bench_paper}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -147,6 +147,23 @@ pg_status pg_mesh_batch_plan(pg_plan* plan, int32_t n_inst, const pg_instance* i
                              const int32_t* conn, const void* B, const void* w, pg_dtype dtype,
                              const pg_options* opts, size_t* workspace_bytes);
 
+/* The paper's section 4 example, with both of its inputs active:
+ *   f(x, b) = || A (3 x) - b ||^2,  A the n x n 1D Laplacian (2 on the
+ *   diagonal, -1 on the first off-diagonals, rows truncated at both ends),
+ *   df/dx = 6 A (3 A x - b),  df/db = -2 (3 A x - b).
+ * options.adjoint: PG_ADJ_GATHER or PG_ADJ_AUTO (each thread recomputes its
+ * neighbours' residuals and writes its own gradient entry: the reverse
+ * threads rescheduled), or PG_ADJ_ATOMIC (the paper's schedule: every
+ * residual scatters into three entries of df/dx with atomic adds).
+ * x, b, gx, gb: n entries of the plan dtype. */
+pg_status pg_laplace1d_plan(pg_plan* plan, int64_t n, pg_dtype dtype, const pg_options* opts,
+                            size_t* workspace_bytes);
+pg_status pg_laplace1d_objective(pg_plan plan, const void* x, const void* b, double* f_out,
+                                 pg_stream stream);
+/* gx (df/dx) and gb (df/db) may each be NULL; f_out may be NULL. */
+pg_status pg_laplace1d_gradient(pg_plan plan, const void* x, const void* b, void* gx, void* gb,
+                                double* f_out, pg_stream stream);
+
 /* Workspace size of a plan (host out). */
 pg_status pg_workspace_size(pg_plan plan, size_t* workspace_bytes);
 

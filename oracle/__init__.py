@@ -66,6 +66,8 @@ def lib():
         L.orc_dense_objective.argtypes = [_I64, _I64, _d, _d, _d, _d, _d]
         L.orc_dense_gradient.argtypes = [_I64, _I64, _d, _d, _d, ctypes.c_double, _d, _d]
         L.orc_bdense_columns.argtypes = [_I64, _I64, _d, _d, _d, _I64, _i64p, _d, _d]
+        L.orc_laplace1d_gradient.argtypes = [_I64, _d, _d, ctypes.c_double, _d, _d, _d]
+        L.orc_laplace1d_gradient.restype = ctypes.c_int
         L.orc_sum.argtypes = [_I64, _d]
         L.orc_sum.restype = ctypes.c_double
         for name in ("orc_mesh_check", "orc_mesh_gather", "orc_mesh_scatter", "orc_mesh_terms",
@@ -278,3 +280,17 @@ def bdense_gradient_fast(A, X, W, fbar: float = 1.0) -> Tuple[float, np.ndarray]
     f = fsum(t)
     V = fbar * W * dpsi(Y.ravel()).reshape(Y.shape)
     return f, A.T @ V
+
+
+# ------------------------------------------- the paper's section 4 example
+
+def laplace1d_gradient(x, b, fbar: float = 1.0):
+    """f(x, b) = ||A(3x) - b||^2 (A: 1D Laplacian), and its gradients in x and b."""
+    x, b = _f64(x), _f64(b)
+    n = x.size
+    f = np.zeros(1)
+    gx = np.empty(n)
+    gb = np.empty(n)
+    _chk(lib().orc_laplace1d_gradient(n, _p(x), _p(b), float(fbar), _p(f), _p(gx), _p(gb)),
+         "laplace1d")
+    return float(f[0]), gx, gb

@@ -398,3 +398,40 @@ double orc_sum(int64_t n, const double* a) {
     for (int64_t i = 0; i < n; ++i) nsum_add(&acc, a[i]);
     return nsum_get(&acc);
 }
+
+/* ------------------------------------------- the paper's section 4 example */
+
+/* f(x, b) = || A (3x) - b ||^2 with A the n x n 1D Laplacian (2 on the
+ * diagonal, -1 on the first off-diagonals, rows truncated at both ends, as the
+ * `j != 0` / `j != n-1` guards of the example do).  Its reverse pass:
+ * ybar = 2 y (reverse of the square and of the sum, seed fbar), then the
+ * transposed stencil for xbar (A is symmetric) times 3, and bbar = -ybar.
+ * gx and gb are overwritten; either may be NULL. */
+int orc_laplace1d_gradient(int64_t n, const double* x, const double* b, double fbar,
+                           double* f_out, double* gx, double* gb) {
+    if (n < 0 || (n > 0 && (!x || !b))) return ORC_EINVAL;
+    double* y = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!y) return ORC_EINVAL;
+    nsum_t acc = {0.0, 0.0};
+    for (int64_t j = 0; j < n; ++j) {
+        double v = 2.0 * (3.0 * x[j]) - b[j];
+        if (j != 0) v = v - 3.0 * x[j - 1];
+        if (j != n - 1) v = v - 3.0 * x[j + 1];
+        y[j] = v;
+        nsum_add(&acc, v * v);
+    }
+    if (f_out) *f_out = nsum_get(&acc);
+    for (int64_t j = 0; j < n; ++j) y[j] = fbar * 2.0 * y[j];  /* ybar */
+    if (gx) {
+        for (int64_t i = 0; i < n; ++i) {
+            double v = 2.0 * y[i];
+            if (i != 0) v = v - y[i - 1];
+            if (i != n - 1) v = v - y[i + 1];
+            gx[i] = 3.0 * v;
+        }
+    }
+    if (gb)
+        for (int64_t j = 0; j < n; ++j) gb[j] = -y[j];
+    free(y);
+    return ORC_OK;
+}

@@ -10,12 +10,12 @@ from __future__ import annotations
 import importlib
 
 __all__ = ["MeshObjective", "DenseObjective", "BatchedDense", "MeshBatch", "MeshFn", "DenseFn",
-           "BatchedDenseFn", "MeshBatchFn", "PgError", "lib"]
+           "BatchedDenseFn", "MeshBatchFn", "Laplace1D", "PgError", "lib"]
 
 
 def __getattr__(name):
     if name in __all__:
         return getattr(importlib.import_module(__name__ + ".pgrad"), name)
-    if name in ("inputs", "pgrad", "build"):
+    if name in ("inputs", "pgrad", "build", "autotune"):
         return importlib.import_module(__name__ + "." + name)
     raise AttributeError(name)

@@ -33,7 +33,7 @@ pg_status fail(pg_status s, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail(PG_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
-enum Kind { K_MESH = 1, K_DENSE = 2, K_BDENSE = 3, K_BATCH = 4 };
+enum Kind { K_MESH = 1, K_DENSE = 2, K_BDENSE = 3, K_BATCH = 4, K_LAPLACE = 5 };
 
 constexpr size_t kAlign = PG_WORKSPACE_ALIGN;
 
@@ -80,6 +80,9 @@ struct pg_plan_s {
     DenseView dense;
     int dense_groups = 0;
     bool dense_fused = false;
+    // the section 4 example
+    int64_t lap_n = 0;
+    bool lap_atomic = false;
     // batched dense
     BDenseView bd;
     int64_t bd_tiles = 0;
@@ -276,6 +279,7 @@ size_t x_bytes(pg_plan p) {
         case K_BATCH: return esize(p->dtype) * (size_t)p->n_nodes_total;
         case K_DENSE: return esize(p->dtype) * (size_t)p->dense.cols;
         case K_BDENSE: return esize(p->dtype) * (size_t)(p->bd.m * p->bd.n);
+        case K_LAPLACE: return esize(p->dtype) * (size_t)p->lap_n;
     }
     return 0;
 }
@@ -630,6 +634,8 @@ pg_status run_kind(pg_plan p, const void* x, const double* fbar, void* grad, dou
         case K_BATCH: return batch_run(p, x, fbar, grad, f_out, want, s);
         case K_DENSE: return dense_run(p, x, fbar, grad, f_out, want, s);
         case K_BDENSE: return bdense_run(p, x, fbar, grad, f_out, want, s);
+        case K_LAPLACE:
+            return fail(PG_EUNSUPPORTED, "use pg_laplace1d_objective / pg_laplace1d_gradient");
     }
     return fail(PG_EINVAL, "unknown plan kind");
 }
@@ -818,7 +824,8 @@ pg_status pg_bind_workspace(pg_plan p, void* workspace, size_t bytes, pg_stream 
         case K_MESH: st = mesh_bind(p, s); break;
         case K_BATCH: st = batch_bind(p, s); break;
         case K_DENSE:
-        case K_BDENSE: break;
+        case K_BDENSE:
+        case K_LAPLACE: break;
     }
     if (st == PG_OK) p->bound = true;
     return st;
@@ -906,6 +913,102 @@ pg_status pg_timing_read(pg_plan p, double* total_ms, int64_t* count) {
     *total_ms = tot;
     *count = p->ev_n;
     p->ev_n = 0;
+    return PG_OK;
+}
+
+pg_status pg_laplace1d_plan(pg_plan* plan, int64_t n, pg_dtype dtype, const pg_options* opts,
+                            size_t* workspace_bytes) {
+    g_err[0] = 0;
+    if (!plan || !workspace_bytes) return fail(PG_EINVAL, "plan and workspace_bytes must not be NULL");
+    pg_status st = check_dtype(dtype);
+    if (st) return st;
+    const int32_t want = opts ? opts->adjoint : PG_ADJ_AUTO;
+    pg_options o;
+    if ((st = check_opts(opts, &o))) return st;
+    if (want == PG_ADJ_COLOUR) return fail(PG_EUNSUPPORTED, "no colour schedule for this example");
+    if (n < 0 || n >= (1LL << 40)) return fail(PG_EINVAL, "n out of range");
+    pg_plan_s* p = new_plan(K_LAPLACE, dtype, o);
+    if (!p) return fail(PG_EINVAL, "out of host memory");
+    p->lap_n = n;
+    p->lap_atomic = want == PG_ADJ_ATOMIC;
+    Layout L;
+    p->n_partials = (size_t)std::max<int64_t>(laplace1d_blocks(n), 1);
+    p->o_partials = L.take(sizeof(double) * p->n_partials);
+    if (p->lap_atomic && dtype == PG_F32) p->o_gacc = L.take(sizeof(double) * (size_t)n);
+    p->ws_bytes = L.total;
+    *workspace_bytes = p->ws_bytes;
+    *plan = p;
+    return PG_OK;
+}
+
+namespace {
+pg_status laplace_args(pg_plan p, const void* x, const void* b) {
+    pg_status st = need_bound(p);
+    if (st) return st;
+    if (p->kind != K_LAPLACE) return fail(PG_EUNSUPPORTED, "not a pg_laplace1d_plan");
+    if (p->lap_n > 0 && (!x || !b)) return fail(PG_EINVAL, "x and b must not be NULL");
+    return PG_OK;
+}
+}  // namespace
+
+pg_status pg_laplace1d_objective(pg_plan p, const void* x, const void* b, double* f_out,
+                                 pg_stream stream) {
+    g_err[0] = 0;
+    pg_status st = laplace_args(p, x, b);
+    if (st) return st;
+    if (!f_out) return fail(PG_EINVAL, "f_out is NULL");
+    const size_t xb = x_bytes(p);
+    if (overlap(f_out, 8, x, xb) || overlap(f_out, 8, b, xb) || overlap(f_out, 8, p->ws, p->ws_bytes))
+        return fail(PG_EALIAS, "f_out overlaps an input or the workspace");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* partials = p->at<double>(p->o_partials);
+    const Dtype dt = p->dtype == PG_F64 ? F64 : F32;
+    PG_HIP(tmark(p, 2, true, s));
+    PG_HIP(tmark(p, 1, true, s));
+    PG_HIP(launch_laplace1d(p->lap_n, dt, 0, x, b, nullptr, nullptr, nullptr, nullptr, partials, 0, s));
+    PG_HIP(tmark(p, 1, false, s));
+    PG_HIP(launch_final_sum(partials, laplace1d_blocks(p->lap_n), f_out, s));
+    PG_HIP(tmark(p, 2, false, s));
+    return PG_OK;
+}
+
+pg_status pg_laplace1d_gradient(pg_plan p, const void* x, const void* b, void* gx, void* gb,
+                                double* f_out, pg_stream stream) {
+    g_err[0] = 0;
+    pg_status st = laplace_args(p, x, b);
+    if (st) return st;
+    const size_t xb = x_bytes(p);
+    const void* outs[3] = {gx, gb, f_out};
+    const size_t ob[3] = {xb, xb, 8};
+    for (int i = 0; i < 3; ++i) {
+        if (overlap(outs[i], ob[i], x, xb) || overlap(outs[i], ob[i], b, xb) ||
+            overlap(outs[i], ob[i], p->ws, p->ws_bytes))
+            return fail(PG_EALIAS, "an output overlaps an input or the workspace");
+        for (int j = 0; j < i; ++j)
+            if (overlap(outs[i], ob[i], outs[j], ob[j])) return fail(PG_EALIAS, "outputs overlap");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* partials = p->at<double>(p->o_partials);
+    const Dtype dt = p->dtype == PG_F64 ? F64 : F32;
+    const int acc = p->opt.accumulate;
+    PG_HIP(tmark(p, 2, true, s));
+    if (p->lap_atomic) {
+        double* g64 = nullptr;
+        if (gx) {
+            g64 = dt == F64 ? static_cast<double*>(gx) : p->at<double>(p->o_gacc);
+            if (dt == F32 || !acc) PG_HIP(launch_zero(g64, sizeof(double) * (size_t)p->lap_n, s));
+        }
+        PG_HIP(tmark(p, 1, true, s));
+        PG_HIP(launch_laplace1d(p->lap_n, dt, 2, x, b, g64, nullptr, gb, nullptr, partials, acc, s));
+        PG_HIP(tmark(p, 1, false, s));
+        if (gx && dt == F32) PG_HIP(launch_f64_to_f32(g64, static_cast<float*>(gx), p->lap_n, acc, s));
+    } else {
+        PG_HIP(tmark(p, 1, true, s));
+        PG_HIP(launch_laplace1d(p->lap_n, dt, 1, x, b, nullptr, gx, gb, nullptr, partials, acc, s));
+        PG_HIP(tmark(p, 1, false, s));
+    }
+    if (f_out) PG_HIP(launch_final_sum(partials, laplace1d_blocks(p->lap_n), f_out, s));
+    PG_HIP(tmark(p, 2, false, s));
     return PG_OK;
 }
 

@@ -13,6 +13,7 @@
 #include <type_traits>
 
 #include "elem_tile.hpp"
+#include "persist.hpp"
 
 namespace pg {
 
@@ -102,24 +103,20 @@ k_batch_persistent_dyn(BatchView bv, BatchPass p) {
     }
 }
 
-// Persistent grid: as many workgroups as the device holds at once (compute
-// units x resident workgroups per unit for this kernel), capped by the tiles.
-template <typename Kern>
-unsigned resident_grid(Kern kern, int block, int64_t n_tiles, int cap) {
-    int dev = 0, cus = 256, occ = 1;
-    if (hipGetDevice(&dev) == hipSuccess)
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, 0) != hipSuccess || occ < 1)
-        occ = 1;
-    int64_t g = (int64_t)cus * occ;
-    if (cap > 0 && g > cap) g = cap;
-    if (g > n_tiles) g = n_tiles;
-    return (unsigned)(g < 1 ? 1 : g);
-}
-
 template <typename T, int K, int MODE, int EPT>
 hipError_t launch_agg(const BatchView& b, const BatchPass& p, hipStream_t s) {
     const bool agg = is_atomic(MODE) && p.combine && (int64_t)p.block * EPT * K <= 2 * kAggSlots;
+    if constexpr (is_atomic(MODE) && EPT == 1) {
+        if (agg) {
+            BatchTiles tiles{b.tiles, b.n_tiles};
+            TileArgs a{b.conn, b.B, b.w, p.x, nullptr, p.u_in, nullptr, nullptr,
+                       static_cast<double*>(p.grad), nullptr};
+            auto kern = k_atomic_persistent<T, K, MODE, BatchTiles>;
+            hipLaunchKernelGGL(kern, dim3(resident_grid(kern, p.block, b.n_tiles, p.grid)),
+                               dim3(p.block), 0, s, tiles, a, p.fbar, 1, p.partials);
+            return hipGetLastError();
+        }
+    }
     if (agg) {
         auto kern = k_batch_persistent<T, K, MODE, EPT, true>;
         hipLaunchKernelGGL(kern, dim3(resident_grid(kern, p.block, b.n_tiles, p.grid)),

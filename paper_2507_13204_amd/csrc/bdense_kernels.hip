@@ -11,6 +11,8 @@
 // nonlinearity and its derivative are fused into the forward epilogue, so
 // neither Y nor psi(Y) round-trips through HBM; the objective is reduced per
 // tile and then in a fixed order (deterministic).
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "launch.hpp"
 
@@ -56,16 +58,30 @@ constexpr int kPerThread = BM * BK / NTHR;  // 8
 
 enum Epi { EPI_FWD = 0, EPI_BWD = 1 };
 
+// One k-tile of both operands staged in registers on its way to LDS.
+template <typename T>
+struct Stage {
+    T a[kPerThread];
+    T b[kPerThread];
+};
+
 // C[M x N] = op(A)[M x K] * Bm[K x N].
 //   TRANS_A == false: op(A)[i][k] = A[i * lda + k]   (forward, A is m x m)
 //   TRANS_A == true:  op(A)[i][k] = A[k * lda + i]   (backward, A^T)
-template <typename T, bool TRANS_A, int EPI>
+// FULL: every tile is in bounds and rows are 16-byte aligned, so operands are
+// read with 16-byte vector loads and no bounds checks.  The k loop keeps two
+// tiles in flight in registers (loaded two steps ahead) on top of the LDS
+// double buffer: at one workgroup per compute unit the matrix-core time of a
+// k-step is shorter than the latency of its loads.
+template <typename T, bool TRANS_A, int EPI, bool FULL>
 __global__ void __launch_bounds__(NTHR)
 k_gemm_mfma(const T* __restrict__ A, const T* __restrict__ Bm, int64_t M, int64_t N, int64_t K,
             const T* __restrict__ W, double* __restrict__ partials, T* __restrict__ Vout,
             const double* __restrict__ fbar, T* __restrict__ Gout, int accumulate) {
     using MF = Mfma<T>;
     using acc_t = typename MF::acc_t;
+    constexpr int VN = 16 / sizeof(T);
+    constexpr int NV = kPerThread / VN;  // vectors per operand per thread
     __shared__ T As[2][BK][BM + PAD];
     __shared__ T Bs[2][BK][BN + PAD];
     __shared__ double red[NTHR / kWave];
@@ -75,36 +91,19 @@ k_gemm_mfma(const T* __restrict__ A, const T* __restrict__ Bm, int64_t M, int64_
     const int wm = wid >> 1, wn = wid & 1;  // wave's 64 x 64 block within the tile
     const int64_t i0 = (int64_t)blockIdx.y * BM, j0 = (int64_t)blockIdx.x * BN;
 
-    // Global -> register staging of one k-tile.
-    T ra[kPerThread], rb[kPerThread];
-    auto gload = [&](int64_t k0) {
-#pragma unroll
-        for (int q = 0; q < kPerThread; ++q) {
-            const int p = tid + NTHR * q;  // 0 .. 2047
-            // A tile: element (i, k) with i in [0,BM), k in [0,BK)
-            int ii, kk;
-            if (TRANS_A) {  // contiguous along i in memory
-                kk = p / BM;
-                ii = p % BM;
-            } else {  // contiguous along k in memory
-                ii = p / BK;
-                kk = p % BK;
+    // Element q of this thread's share of a tile, as (i, k) of op(A) and (k, j) of B.
+    auto a_coord = [&](int q, int& ii, int& kk) {
+        if constexpr (FULL) {
+            const int v = tid + NTHR * (q / VN), c = q % VN;
+            if (TRANS_A) {
+                kk = v / (BM / VN);
+                ii = (v % (BM / VN)) * VN + c;
+            } else {
+                ii = v / (BK / VN);
+                kk = (v % (BK / VN)) * VN + c;
             }
-            const int64_t gi = i0 + ii, gk = k0 + kk;
-            T va = T(0);
-            if (gi < M && gk < K) va = TRANS_A ? A[gk * K + gi] : A[gi * K + gk];
-            ra[q] = va;
-            // B tile: element (k, j), contiguous along j
-            const int bk = p / BN, bj = p % BN;
-            const int64_t gk2 = k0 + bk, gj = j0 + bj;
-            rb[q] = (gk2 < K && gj < N) ? Bm[gk2 * N + gj] : T(0);
-        }
-    };
-    auto lstore = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < kPerThread; ++q) {
+        } else {
             const int p = tid + NTHR * q;
-            int ii, kk;
             if (TRANS_A) {
                 kk = p / BM;
                 ii = p % BM;
@@ -112,8 +111,61 @@ k_gemm_mfma(const T* __restrict__ A, const T* __restrict__ Bm, int64_t M, int64_
                 ii = p / BK;
                 kk = p % BK;
             }
-            As[buf][kk][ii] = ra[q];
-            Bs[buf][p / BN][p % BN] = rb[q];
+        }
+    };
+    auto b_coord = [&](int q, int& kk, int& jj) {
+        if constexpr (FULL) {
+            const int v = tid + NTHR * (q / VN), c = q % VN;
+            kk = v / (BN / VN);
+            jj = (v % (BN / VN)) * VN + c;
+        } else {
+            const int p = tid + NTHR * q;
+            kk = p / BN;
+            jj = p % BN;
+        }
+    };
+    auto gload = [&](Stage<T>& st, int64_t k0) {
+        if constexpr (FULL) {
+            using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                int ii, kk, bk, bj;
+                a_coord(v * VN, ii, kk);
+                b_coord(v * VN, bk, bj);
+                const T* pa = TRANS_A ? A + (k0 + kk) * K + (i0 + ii) : A + (i0 + ii) * K + (k0 + kk);
+                const V va = *reinterpret_cast<const V*>(pa);
+                const V vb = *reinterpret_cast<const V*>(Bm + (k0 + bk) * N + (j0 + bj));
+                const T* ea = reinterpret_cast<const T*>(&va);
+                const T* eb = reinterpret_cast<const T*>(&vb);
+#pragma unroll
+                for (int c = 0; c < VN; ++c) {
+                    st.a[v * VN + c] = ea[c];
+                    st.b[v * VN + c] = eb[c];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < kPerThread; ++q) {
+                int ii, kk, bk, bj;
+                a_coord(q, ii, kk);
+                b_coord(q, bk, bj);
+                const int64_t gi = i0 + ii, gk = k0 + kk;
+                T va = T(0);
+                if (gi < M && gk < K) va = TRANS_A ? A[gk * K + gi] : A[gi * K + gk];
+                st.a[q] = va;
+                const int64_t gk2 = k0 + bk, gj = j0 + bj;
+                st.b[q] = (gk2 < K && gj < N) ? Bm[gk2 * N + gj] : T(0);
+            }
+        }
+    };
+    auto lstore = [&](const Stage<T>& st, int buf) {
+#pragma unroll
+        for (int q = 0; q < kPerThread; ++q) {
+            int ii, kk, bk, bj;
+            a_coord(q, ii, kk);
+            b_coord(q, bk, bj);
+            As[buf][kk][ii] = st.a[q];
+            Bs[buf][bk][bj] = st.b[q];
         }
     };
 
@@ -123,16 +175,8 @@ k_gemm_mfma(const T* __restrict__ A, const T* __restrict__ Bm, int64_t M, int64_
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = MF::zero();
 
-    const int64_t nk = (K + BK - 1) / BK;
-    if (nk > 0) {
-        gload(0);
-        lstore(0);
-    }
-    __syncthreads();
     const int li = lane & 15, lk = lane >> 4;
-    for (int64_t t = 0; t < nk; ++t) {
-        const int buf = (int)(t & 1);
-        if (t + 1 < nk) gload((t + 1) * BK);
+    auto compute = [&](int buf) {
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
             T a[4], b[4];
@@ -146,7 +190,26 @@ k_gemm_mfma(const T* __restrict__ A, const T* __restrict__ Bm, int64_t M, int64_
 #pragma unroll
                 for (int y = 0; y < 4; ++y) acc[x][y] = MF::mac(a[x], b[y], acc[x][y]);
         }
-        if (t + 1 < nk) lstore(buf ^ 1);
+    };
+
+    // Tile j lives in stage j % 2 and LDS buffer j % 2.
+    const int64_t nk = (K + BK - 1) / BK;
+    Stage<T> s0, s1;
+    if (nk > 0) gload(s0, 0);
+    if (nk > 1) gload(s1, BK);
+    if (nk > 0) lstore(s0, 0);
+    __syncthreads();
+    for (int64_t t = 0; t < nk; t += 2) {
+        // even step: compute tile t from buffer 0; tile t+1 waits in s1
+        if (t + 2 < nk) gload(s0, (t + 2) * BK);
+        compute(0);
+        if (t + 1 < nk) lstore(s1, 1);
+        __syncthreads();
+        if (t + 1 >= nk) break;
+        // odd step: compute tile t+1 from buffer 1; tile t+2 waits in s0
+        if (t + 3 < nk) gload(s1, (t + 3) * BK);
+        compute(1);
+        if (t + 2 < nk) lstore(s0, 0);
         __syncthreads();
     }
 
@@ -188,18 +251,39 @@ k_gemm_mfma(const T* __restrict__ A, const T* __restrict__ Bm, int64_t M, int64_
 
 int64_t bdense_fwd_tiles(int64_t m, int64_t n) { return ((m + BM - 1) / BM) * ((n + BN - 1) / BN); }
 
+namespace {
+
+// Vector path: whole tiles only, and the per-call operand (X or V) 16-byte
+// aligned (A and W are checked when the plan is made).
+bool full_tiles(const BDenseView& b, const void* op) {
+    return b.m % BM == 0 && b.n % BN == 0 && b.m % BK == 0 && (uintptr_t)op % 16 == 0;
+}
+
+template <typename T, bool TRANS, int EPI>
+void launch_gemm(const BDenseView& b, dim3 grid, hipStream_t s, const T* A, const T* Bm, const T* W,
+                 double* partials, T* V, const double* fbar, T* G, int accumulate) {
+    if (full_tiles(b, Bm))
+        hipLaunchKernelGGL((k_gemm_mfma<T, TRANS, EPI, true>), grid, dim3(NTHR), 0, s, A, Bm, b.m,
+                           b.n, b.m, W, partials, V, fbar, G, accumulate);
+    else
+        hipLaunchKernelGGL((k_gemm_mfma<T, TRANS, EPI, false>), grid, dim3(NTHR), 0, s, A, Bm, b.m,
+                           b.n, b.m, W, partials, V, fbar, G, accumulate);
+}
+
+}  // namespace
+
 hipError_t launch_bdense_fwd(const BDenseView& b, const void* X, double* partials, void* V,
                              hipStream_t s) {
     if (b.m == 0 || b.n == 0) return hipSuccess;
     const dim3 grid((unsigned)((b.n + BN - 1) / BN), (unsigned)((b.m + BM - 1) / BM));
     if (b.dtype == F64)
-        hipLaunchKernelGGL((k_gemm_mfma<double, false, EPI_FWD>), grid, dim3(NTHR), 0, s,
-                           (const double*)b.A, (const double*)X, b.m, b.n, b.m, (const double*)b.W,
-                           partials, (double*)V, nullptr, nullptr, 0);
+        launch_gemm<double, false, EPI_FWD>(b, grid, s, (const double*)b.A, (const double*)X,
+                                            (const double*)b.W, partials, (double*)V, nullptr,
+                                            nullptr, 0);
     else
-        hipLaunchKernelGGL((k_gemm_mfma<float, false, EPI_FWD>), grid, dim3(NTHR), 0, s,
-                           (const float*)b.A, (const float*)X, b.m, b.n, b.m, (const float*)b.W,
-                           partials, (float*)V, nullptr, nullptr, 0);
+        launch_gemm<float, false, EPI_FWD>(b, grid, s, (const float*)b.A, (const float*)X,
+                                           (const float*)b.W, partials, (float*)V, nullptr,
+                                           nullptr, 0);
     return hipGetLastError();
 }
 
@@ -208,13 +292,11 @@ hipError_t launch_bdense_bwd(const BDenseView& b, const void* V, const double* f
     if (b.m == 0 || b.n == 0) return hipSuccess;
     const dim3 grid((unsigned)((b.n + BN - 1) / BN), (unsigned)((b.m + BM - 1) / BM));
     if (b.dtype == F64)
-        hipLaunchKernelGGL((k_gemm_mfma<double, true, EPI_BWD>), grid, dim3(NTHR), 0, s,
-                           (const double*)b.A, (const double*)V, b.m, b.n, b.m, nullptr, nullptr,
-                           nullptr, fbar, (double*)G, accumulate);
+        launch_gemm<double, true, EPI_BWD>(b, grid, s, (const double*)b.A, (const double*)V, nullptr,
+                                           nullptr, nullptr, fbar, (double*)G, accumulate);
     else
-        hipLaunchKernelGGL((k_gemm_mfma<float, true, EPI_BWD>), grid, dim3(NTHR), 0, s,
-                           (const float*)b.A, (const float*)V, b.m, b.n, b.m, nullptr, nullptr,
-                           nullptr, fbar, (float*)G, accumulate);
+        launch_gemm<float, true, EPI_BWD>(b, grid, s, (const float*)b.A, (const float*)V, nullptr,
+                                          nullptr, nullptr, fbar, (float*)G, accumulate);
     return hipGetLastError();
 }
 

@@ -170,3 +170,17 @@ hipError_t launch_bdense_bwd(const BDenseView& b, const void* V, const double* f
                              int accumulate, hipStream_t s);
 
 }  // namespace pg
+
+namespace pg {
+
+// ------------------------------------------- the paper's section 4 example
+
+// mode 0: objective; 1: gradient (gather form, writes gx / gb of dtype);
+// 2: gradient (atomic form: FP64 atomics into gx64, which must be zeroed
+// or hold the values to add to; gb of dtype).  partials: one per 256 nodes.
+int64_t laplace1d_blocks(int64_t n);
+hipError_t launch_laplace1d(int64_t n, Dtype dt, int mode, const void* x, const void* b,
+                            double* gx64, void* gx, void* gb, const double* fbar,
+                            double* partials, int accumulate, hipStream_t s);
+
+}  // namespace pg

@@ -17,6 +17,7 @@
 #include <type_traits>
 
 #include "elem_tile.hpp"
+#include "persist.hpp"
 
 namespace pg {
 
@@ -300,10 +301,20 @@ hipError_t launch_elem_t(const MeshView& m, const MeshPass& p, hipStream_t s) {
     const int64_t n_items = p.elist ? p.elist_n : m.n_elems;
     const int64_t nb = mesh_blocks(n_items, p.block, EPT);
     if (nb == 0) return hipSuccess;
-    // Combine in LDS when the workgroup's contributions fill at most half the table.
     // Combine in LDS when the workgroup's contributions fit the table twice over
     // at worst (all distinct); meshes with locality fill it far less.
     const bool agg = is_atomic(MODE) && p.combine && (int64_t)p.block * EPT * K <= 2 * kAggSlots;
+    if constexpr ((MODE == M_GRAD_ATOMIC || MODE == M_ADJ_ATOMIC) && EPT == 1) {
+        if (agg && !p.elist) {
+            // Persistent pipelined pass: tile t is workgroup-sized, partial slot t.
+            MeshTiles tiles{m.n_elems, p.block, nb};
+            TileArgs a{m.conn, m.B, m.w, p.x, nullptr, p.u_in, nullptr, nullptr, p.gacc, nullptr};
+            auto kern = k_atomic_persistent<T, K, MODE, MeshTiles>;
+            hipLaunchKernelGGL(kern, dim3(resident_grid(kern, p.block, nb, 0)), dim3(p.block), 0, s,
+                               tiles, a, p.fbar, 0, p.partials + p.partial_base);
+            return hipGetLastError();
+        }
+    }
     if (agg)
         hipLaunchKernelGGL((k_mesh_elem<T, K, MODE, EPT, true>), dim3((unsigned)nb), dim3(p.block), 0,
                            s, m, p);

@@ -33,6 +33,7 @@ CKPTS = {"recompute": RECOMPUTE, "store": STORE}
 EXPORTS = ("pg_default_options", "pg_mesh_plan", "pg_dense_plan", "pg_bdense_plan",
            "pg_mesh_batch_plan", "pg_workspace_size", "pg_bind_workspace", "pg_objective",
            "pg_gradient", "pg_adjoint", "pg_hvp", "pg_timing", "pg_timing_read",
+           "pg_laplace1d_plan", "pg_laplace1d_objective", "pg_laplace1d_gradient",
            "pg_plan_destroy", "pg_last_error", "pg_version")
 
 
@@ -88,13 +89,17 @@ def lib():
     L.pg_plan_destroy.argtypes = [_VP]
     L.pg_timing.argtypes = [_VP, _I32]
     L.pg_timing_read.argtypes = [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]
+    L.pg_laplace1d_plan.argtypes = [_PLANP, _I64, ctypes.c_int, OP, _SZP]
+    L.pg_laplace1d_objective.argtypes = [_VP, _VP, _VP, _VP, _VP]
+    L.pg_laplace1d_gradient.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP]
     L.pg_last_error.restype = ctypes.c_char_p
     L.pg_last_error.argtypes = []
     L.pg_version.restype = ctypes.c_int
     L.pg_version.argtypes = []
     for name in ("pg_mesh_plan", "pg_dense_plan", "pg_bdense_plan", "pg_mesh_batch_plan",
                  "pg_workspace_size", "pg_bind_workspace", "pg_objective", "pg_gradient",
-                 "pg_adjoint", "pg_hvp", "pg_timing", "pg_timing_read", "pg_plan_destroy"):
+                 "pg_adjoint", "pg_hvp", "pg_timing", "pg_timing_read", "pg_plan_destroy",
+                 "pg_laplace1d_plan", "pg_laplace1d_objective", "pg_laplace1d_gradient"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -340,6 +345,44 @@ class MeshBatch(_Plan):
     def adjoint(self, x, fbar, out=None, stream=None):
         _need_cuda(x, fbar, out)
         return self._adjoint(x, fbar, out, stream)
+
+
+class Laplace1D(_Plan):
+    """The paper's section 4 example: f(x, b) = ||A(3x) - b||^2, A the 1D
+    Laplacian; gradients in x and b.  adjoint: 'gather' (default, rescheduled
+    reverse threads) or 'atomic' (the paper's scatter schedule)."""
+
+    def __init__(self, n: int, dtype=torch.float64, adjoint="gather", accumulate: bool = False,
+                 device="cuda", stream=None):
+        super().__init__()
+        self.n = int(n)
+        self.dtype = dtype
+        code = F64 if dtype == torch.float64 else F32 if dtype == torch.float32 else -1
+        self.options = make_options(adjoint=adjoint, accumulate=accumulate)
+        sz = ctypes.c_size_t()
+        check(lib().pg_laplace1d_plan(ctypes.byref(self._plan), self.n, code,
+                                      ctypes.byref(self.options), ctypes.byref(sz)),
+              "pg_laplace1d_plan")
+        self.workspace_bytes = sz.value
+        self._bind(torch.device(device), stream)
+
+    def objective(self, x, b, stream=None, f_out=None):
+        _need_cuda(x, b)
+        f = torch.empty((), dtype=torch.float64, device=x.device) if f_out is None else f_out
+        check(lib().pg_laplace1d_objective(self._plan, _ptr(x), _ptr(b), _ptr(f), _stream(stream)),
+              "pg_laplace1d_objective")
+        return f
+
+    def gradient(self, x, b, gx=None, gb=None, want=("x", "b"), stream=None, f_out=None):
+        _need_cuda(x, b, gx, gb)
+        if gx is None and "x" in want:
+            gx = torch.empty_like(x)
+        if gb is None and "b" in want:
+            gb = torch.empty_like(b)
+        f = torch.empty((), dtype=torch.float64, device=x.device) if f_out is None else f_out
+        check(lib().pg_laplace1d_gradient(self._plan, _ptr(x), _ptr(b), _ptr(gx), _ptr(gb),
+                                          _ptr(f), _stream(stream)), "pg_laplace1d_gradient")
+        return f, gx, gb
 
 
 # ------------------------------------------------------------------ autograd

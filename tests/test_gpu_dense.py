@@ -97,3 +97,17 @@ def test_bdense_full_size_sampled_columns():
         assert rel(Gh[:, c], Gc[:, t]) <= TOL_F64_G
     f_ref, _ = oracle.bdense_gradient_fast(b.A, b.X, b.W)
     assert srel(f.item(), f_ref) <= TOL_F64_F
+
+
+def test_bdense_misaligned_operand_takes_the_scalar_path():
+    """X at an 8-byte offset: the vector loads are not used, results still match."""
+    b = inputs.batched_dense(256, 128, seed=57)
+    obj, X = _bdense(b)
+    big = torch.empty(X.numel() + 1, dtype=torch.float64, device="cuda")
+    Xm = big[1:].view(X.shape)
+    Xm.copy_(X)
+    assert Xm.data_ptr() % 16 == 8
+    f, G = obj.gradient(Xm)
+    f_ref, G_ref = oracle.bdense_gradient_fast(b.A, b.X, b.W)
+    assert srel(f.item(), f_ref) <= TOL_F64_F
+    assert rel(G.cpu().numpy(), G_ref) <= TOL_F64_G

@@ -352,3 +352,56 @@ def test_uneven_sides_law():
     assert s.min() >= 10 and s.max() <= 100
     # log-uniform: the median side is near sqrt(10 * 100)
     assert 22 <= np.median(s) <= 42
+
+
+# ------------------------------------------- the paper's section 4 example
+
+def _laplacian(n):
+    return sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1], format="csr")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 1000])
+def test_laplace1d_closed_form(orc, n):
+    """grad_x f = 6 A (3 A x - b) and grad_b f = -2 (3 A x - b), A symmetric."""
+    rng = np.random.default_rng(n)
+    x, b = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    f, gx, gb = orc.laplace1d_gradient(x, b)
+    A = _laplacian(n)
+    y = 3 * (A @ x) - b
+    assert abs(f - math.fsum(y * y)) <= 1e-14 * max(f, 1e-300)
+    assert rel(gx, 6 * (A @ y)) <= 1e-14
+    assert rel(gb, -2 * y) <= 1e-15
+    f2, gx2, gb2 = orc.laplace1d_gradient(x, b, fbar=0.5)
+    assert rel(gx2, 0.5 * gx) <= 1e-15 and rel(gb2, 0.5 * gb) <= 1e-15
+
+
+def test_laplace1d_worked_and_complex_step(orc):
+    # n = 1: A = [2], y = 6x - b, f = y^2, df/dx = 12 y, df/db = -2 y
+    f, gx, gb = orc.laplace1d_gradient([0.25], [0.5])
+    assert f == 1.0 and gx[0] == 12.0 and gb[0] == -2.0
+    # complex step through an independent evaluation of the example's kernels
+    n = 9
+    rng = np.random.default_rng(99)
+    x, b = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+
+    def F(xc, bc):
+        xs = [3 * v for v in xc]
+        tot = 0j
+        for j in range(n):
+            y = 2 * xs[j] - bc[j]
+            if j != 0:
+                y -= xs[j - 1]
+            if j != n - 1:
+                y -= xs[j + 1]
+            tot += y * y
+        return tot
+
+    _, gx, gb = orc.laplace1d_gradient(x, b)
+    h = 1e-30
+    for i in range(n):
+        xc = [complex(v) for v in x]
+        xc[i] += 1j * h
+        assert abs(F(xc, list(b)).imag / h - gx[i]) <= 1e-14 * max(1, abs(gx[i]))
+        bc = [complex(v) for v in b]
+        bc[i] += 1j * h
+        assert abs(F(list(x), bc).imag / h - gb[i]) <= 1e-14 * max(1, abs(gb[i]))
