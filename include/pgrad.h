@@ -198,6 +198,12 @@ pg_status pg_adjoint(pg_plan plan, const void* x, const double* fbar, void* grad
  *   hv = G^T ( w (.) psi''(G x) (.) (G v) ).  Mesh plans only. */
 pg_status pg_hvp(pg_plan plan, const void* x, const void* v, void* hv, pg_stream stream);
 
+/* Forward tangent (directional derivative) of the mesh objective, the other
+ * derivative mode the conclusion names:
+ *   jvp_out[0] (device FP64) = f'(x) . d = sum_e w_e psi'(u_e) (G d)_e.
+ * Mesh plans only; reduced in a fixed order. */
+pg_status pg_jvp(pg_plan plan, const void* x, const void* d, double* jvp_out, pg_stream stream);
+
 /* Measurement hook.  mode 0: off; 1: time the dominant kernel of every
  * subsequent evaluation (the element pass of a mesh or batch, the fused row
  * pass of a dense plan, the forward or backward product of a batched dense

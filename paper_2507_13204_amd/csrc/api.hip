@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -60,6 +61,48 @@ constexpr size_t NONE = ~size_t(0);
 
 }  // namespace
 
+namespace pg {
+
+// Candidate rotations of the LDS table hash, spread over the 4096 slots.
+static const uint32_t kShiftCandidates[] = {2533, 1237, 3371, 615, 1861, 2967, 347, 3779, 1493, 2207,
+                                            3061, 881};
+
+uint32_t choose_hash_shift(const int32_t* const* tiles, const int64_t* counts, int64_t n_tiles) {
+    constexpr int kSlots = 4096, kProbe = 64;
+    std::vector<int32_t> key(kSlots);
+    uint32_t best = kShiftCandidates[0];
+    int64_t best_cost = INT64_MAX;
+    for (uint32_t cand : kShiftCandidates) {
+        int64_t cost = 0;
+        for (int64_t t = 0; t < n_tiles && cost < best_cost; ++t) {
+            std::fill(key.begin(), key.end(), -1);
+            for (int64_t q = 0; q < counts[t]; ++q) {
+                const int32_t n = tiles[t][q];
+                const uint32_t u = (uint32_t)n;
+                uint32_t h = (u + (u >> 12) * cand) & (kSlots - 1);
+                int probe = 0;
+                while (probe < kProbe && key[h] != -1 && key[h] != n) {
+                    h = (h + 1) & (kSlots - 1);
+                    ++probe;
+                }
+                if (probe == kProbe) {
+                    cost += 4 * kProbe;  // spills to a global atomic
+                } else {
+                    key[h] = n;
+                    cost += probe;
+                }
+            }
+        }
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = cand;
+        }
+    }
+    return best;
+}
+
+}  // namespace pg
+
 struct pg_plan_s {
     Kind kind;
     pg_dtype dtype;
@@ -67,6 +110,7 @@ struct pg_plan_s {
     // mesh / batch
     MeshView mesh;
     int64_t mesh_blocks_n = 0;
+    uint32_t hash_shift = 2533;  // LDS table hash parameter chosen at bind time
     // colour classes: elements of colour c are elist[colour_off[c] .. colour_off[c+1])
     std::vector<int64_t> colour_off;
     size_t o_elist = NONE;
@@ -211,7 +255,7 @@ void layout_batch(pg_plan_s* p) {
             const int64_t first = in.elem_off + t * te;
             p->h_tiles.push_back(first);
             p->h_tiles.push_back(std::min(first + te, in.elem_off + in.n_elems));
-            p->h_tiles.push_back(in.node_off);
+            p->h_tiles.push_back(in.node_off | ((int64_t)2533 << 40));
             p->h_tiles.push_back(((int64_t)oi << 40) | (p->h_seg[oi] + t));
         }
     }
@@ -328,6 +372,7 @@ MeshPass base_pass(pg_plan p, const void* x) {
     q.block = p->opt.block;
     q.ept = p->opt.tile;
     q.combine = p->opt.scatter == 0;
+    q.hash_shift = p->hash_shift;
     return q;
 }
 
@@ -409,6 +454,48 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
     return PG_OK;
 }
 
+// ------------------------------------------------- LDS table hash choice
+
+// Node numbers touched by elements [e0, e1) of a connectivity (k per row),
+// offset by noff, copied from the device.
+pg_status sample_nodes(const int32_t* conn, int64_t e0, int64_t e1, int32_t k, int64_t noff,
+                       std::vector<int32_t>& out, hipStream_t s) {
+    out.resize((size_t)((e1 - e0) * k));
+    if (out.empty()) return PG_OK;
+    PG_HIP(hipMemcpyAsync(out.data(), conn + e0 * k, sizeof(int32_t) * out.size(),
+                          hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    if (noff)
+        for (auto& v : out) v = (int32_t)(v + noff);
+    return PG_OK;
+}
+
+// Sampled tiles of one mesh: up to `want` workgroup tiles spread evenly.
+pg_status sample_mesh_tiles(const int32_t* conn, int64_t n_elems, int32_t k, int64_t noff,
+                            int64_t span, int want, std::vector<std::vector<int32_t>>& tiles,
+                            hipStream_t s) {
+    const int64_t nt = (n_elems + span - 1) / span;
+    const int64_t ns = std::min<int64_t>(nt, want);
+    for (int64_t i = 0; i < ns; ++i) {
+        const int64_t t = nt > 1 ? i * (nt - 1) / std::max<int64_t>(ns - 1, 1) : 0;
+        tiles.emplace_back();
+        pg_status st = sample_nodes(conn, t * span, std::min(n_elems, (t + 1) * span), k, noff,
+                                    tiles.back(), s);
+        if (st) return st;
+    }
+    return PG_OK;
+}
+
+uint32_t shift_of(const std::vector<std::vector<int32_t>>& tiles) {
+    std::vector<const int32_t*> ptr;
+    std::vector<int64_t> cnt;
+    for (const auto& t : tiles) {
+        ptr.push_back(t.data());
+        cnt.push_back((int64_t)t.size());
+    }
+    return choose_hash_shift(ptr.data(), cnt.data(), (int64_t)tiles.size());
+}
+
 // Greedy colouring in element order (plan time, on the host): element e
 // takes the smallest colour that no earlier element sharing one of its nodes
 // has.  Node masks record the colours already present at each node, so one
@@ -467,6 +554,13 @@ pg_status mesh_bind(pg_plan p, hipStream_t s) {
     PG_HIP(hipMemcpyAsync(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
     if (hflag) return fail(PG_ERANGE, "connectivity has an entry outside [0, %lld)", (long long)m.n_nodes);
+    if (p->opt.scatter == 0 && m.n_elems > 0) {
+        std::vector<std::vector<int32_t>> tiles;
+        pg_status hst = sample_mesh_tiles(m.conn, m.n_elems, m.k, 0,
+                                          (int64_t)p->opt.block * p->opt.tile, 24, tiles, s);
+        if (hst != PG_OK) return hst;
+        p->hash_shift = shift_of(tiles);
+    }
     if (p->opt.adjoint == PG_ADJ_COLOUR) {
         pg_status cst = mesh_colour(p, s);
         if (cst != PG_OK) return cst;
@@ -493,8 +587,28 @@ pg_status batch_bind(pg_plan p, hipStream_t s) {
         PG_HIP(launch_validate_count(p->batch.conn + in.elem_off * p->batch.k,
                                      in.n_elems * p->batch.k, in.n_nodes, nullptr, flag, s));
     }
-    // Upload the work list and instance tables.
+    // LDS table hash parameter per instance, written into its tile records.
     const int64_t nt = p->batch.n_tiles, ni = (int64_t)p->inst.size();
+    if (p->opt.scatter == 0) {
+        std::vector<uint32_t> shift((size_t)ni, 2533u);
+        for (int64_t i = 0; i < ni; ++i) {
+            const pg_instance& in = p->inst[(size_t)i];
+            if (in.n_elems == 0) continue;
+            std::vector<std::vector<int32_t>> tiles;
+            pg_status hst = sample_mesh_tiles(p->batch.conn + in.elem_off * p->batch.k, in.n_elems,
+                                              p->batch.k, in.node_off, p->batch.tile_elems, 4,
+                                              tiles, s);
+            if (hst != PG_OK) return hst;
+            shift[(size_t)i] = shift_of(tiles);
+        }
+        for (int64_t t = 0; t < nt; ++t) {
+            const int64_t inst = p->h_tiles[(size_t)(4 * t + 3)] >> 40;
+            p->h_tiles[(size_t)(4 * t + 2)] =
+                (p->h_tiles[(size_t)(4 * t + 2)] & ((1LL << 40) - 1)) |
+                ((int64_t)shift[(size_t)inst] << 40);
+        }
+    }
+    // Upload the work list and instance tables.
     std::vector<int64_t> tab;
     tab.reserve((size_t)(4 * nt + ni + 1));
     tab.insert(tab.end(), p->h_tiles.begin(), p->h_tiles.end());
@@ -1009,6 +1123,23 @@ pg_status pg_laplace1d_gradient(pg_plan p, const void* x, const void* b, void* g
     }
     if (f_out) PG_HIP(launch_final_sum(partials, laplace1d_blocks(p->lap_n), f_out, s));
     PG_HIP(tmark(p, 2, false, s));
+    return PG_OK;
+}
+
+pg_status pg_jvp(pg_plan p, const void* x, const void* d, double* jvp_out, pg_stream stream) {
+    g_err[0] = 0;
+    pg_status st = need_bound(p);
+    if (st) return st;
+    if (p->kind != K_MESH) return fail(PG_EUNSUPPORTED, "pg_jvp supports mesh plans only");
+    if ((!x || !d) && x_bytes(p) > 0) return fail(PG_EINVAL, "x and d must not be NULL");
+    if (!jvp_out) return fail(PG_EINVAL, "jvp_out is NULL");
+    if ((st = check_out_alias(p, jvp_out, sizeof(double), x, "jvp_out"))) return st;
+    if (overlap(jvp_out, sizeof(double), d, x_bytes(p))) return fail(PG_EALIAS, "jvp_out overlaps d");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    MeshPass q = base_pass(p, x);
+    q.xd = d;
+    PG_HIP(launch_mesh_elem(p->mesh, M_JVP, q, s));
+    PG_HIP(launch_final_sum(q.partials, p->mesh_blocks_n, jvp_out, s));
     return PG_OK;
 }
 

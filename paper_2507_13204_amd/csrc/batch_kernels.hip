@@ -20,7 +20,7 @@ namespace pg {
 namespace {
 
 struct TileRec {
-    int64_t first, end, noff, slot_inst;
+    int64_t first, end, shift_noff, slot_inst;
 };
 
 __device__ __forceinline__ TileRec load_tile(const int64_t* tiles, int64_t t) {
@@ -30,6 +30,7 @@ __device__ __forceinline__ TileRec load_tile(const int64_t* tiles, int64_t t) {
 }
 
 constexpr int64_t kSlotMask = (1LL << 40) - 1;
+constexpr int64_t kNoffMask = (1LL << 40) - 1;
 
 // Logical workgroup l (XCD-remapped, so l .. l + grid/8 - 1 share an XCD)
 // takes tiles l, l + grid, ...; consecutive tiles of an instance therefore run
@@ -43,7 +44,7 @@ k_batch_persistent(BatchView bv, BatchPass p) {
     AggTable* tab = nullptr;
     if constexpr (AGG) tab = &agg;
     TileArgs a{bv.conn, bv.B, bv.w, p.x, nullptr, p.u_in, p.u_store, nullptr,
-               static_cast<double*>(p.grad), nullptr};
+               static_cast<double*>(p.grad), nullptr, 0u};
     const int64_t G = gridDim.x;
     int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
     TileRec cur{};
@@ -54,7 +55,9 @@ k_batch_persistent(BatchView bv, BatchPass p) {
         const int64_t inst = cur.slot_inst >> 40;
         double fb = 1.0;
         if constexpr (has_rev(MODE)) fb = p.fbar ? p.fbar[inst] : 1.0;
-        const double tsum = elem_tile<T, K, MODE, EPT, AGG>(a, cur.first, cur.end, cur.noff, fb, tab);
+        a.hash_shift = (uint32_t)(cur.shift_noff >> 40);
+        const double tsum = elem_tile<T, K, MODE, EPT, AGG>(a, cur.first, cur.end,
+                                                            cur.shift_noff & kNoffMask, fb, tab);
         if constexpr (has_obj(MODE)) {
             const double s = block_sum_dyn(tsum, lds);
             if (threadIdx.x == 0) p.partials[cur.slot_inst & kSlotMask] = s;
@@ -85,7 +88,7 @@ k_batch_persistent_dyn(BatchView bv, BatchPass p) {
                 u = p.u_in[e];
             } else {
                 for (int j = 0; j < k; ++j)
-                    u += to_f64(B[e * k + j]) * to_f64(X[r.noff + conn[e * k + j]]);
+                    u += to_f64(B[e * k + j]) * to_f64(X[(r.shift_noff & kNoffMask) + conn[e * k + j]]);
                 if (p.u_store) p.u_store[e] = u;
             }
             const double s2 = u * u, wd = to_f64(W[e]);
@@ -93,7 +96,8 @@ k_batch_persistent_dyn(BatchView bv, BatchPass p) {
             if constexpr (has_rev(MODE)) {
                 const double v = (p.fbar ? p.fbar[inst] : 1.0) * wd * dpsi_from(u, s2);
                 for (int j = 0; j < k; ++j)
-                    atomic_add_f64(G + r.noff + conn[e * k + j], v * to_f64(B[e * k + j]));
+                    atomic_add_f64(G + (r.shift_noff & kNoffMask) + conn[e * k + j],
+                                   v * to_f64(B[e * k + j]));
             }
         }
         if constexpr (has_obj(MODE)) {
@@ -110,7 +114,7 @@ hipError_t launch_agg(const BatchView& b, const BatchPass& p, hipStream_t s) {
         if (agg) {
             BatchTiles tiles{b.tiles, b.n_tiles};
             TileArgs a{b.conn, b.B, b.w, p.x, nullptr, p.u_in, nullptr, nullptr,
-                       static_cast<double*>(p.grad), nullptr};
+                       static_cast<double*>(p.grad), nullptr, 0u};
             auto kern = k_atomic_persistent<T, K, MODE, BatchTiles>;
             hipLaunchKernelGGL(kern, dim3(resident_grid(kern, p.block, b.n_tiles, p.grid)),
                                dim3(p.block), 0, s, tiles, a, p.fbar, 1, p.partials);

@@ -14,7 +14,9 @@ namespace pg {
 constexpr bool has_obj(int mode) {
     return mode == M_PRIMAL || mode == M_GRAD_ATOMIC || mode == M_GRAD_V || mode == M_GRAD_COLOUR;
 }
-constexpr bool has_rev(int mode) { return mode != M_PRIMAL && mode != M_HVP; }
+constexpr bool has_rev(int mode) { return mode != M_PRIMAL && mode != M_HVP && mode != M_JVP; }
+// Modes that reduce a per-element quantity into per-workgroup partials.
+constexpr bool has_sum(int mode) { return has_obj(mode) || mode == M_JVP; }
 constexpr bool is_atomic(int mode) { return mode == M_GRAD_ATOMIC || mode == M_ADJ_ATOMIC || mode == M_HVP; }
 constexpr bool is_colour(int mode) { return mode == M_GRAD_COLOUR || mode == M_ADJ_COLOUR; }
 constexpr bool writes_v(int mode) { return mode == M_GRAD_V || mode == M_ADJ_V; }
@@ -105,9 +107,14 @@ struct AggTable {
     double val[kAggSlots];
 };
 
-__device__ __forceinline__ uint32_t agg_hash(int32_t n) {
+// Consecutive node numbers go to consecutive slots (so the flush touches few
+// cache lines per instruction); each further window of 4096 node numbers is
+// rotated by `shift` slots, so ranges that are a plane (or an instance) apart
+// in the numbering land on different slots.  The plan picks `shift` for its
+// connectivity by simulating the table on sampled workgroups.
+__device__ __forceinline__ uint32_t agg_hash(int32_t n, uint32_t shift) {
     const uint32_t u = (uint32_t)n;
-    return (u + (u >> 12) * 2533u) & (kAggSlots - 1);
+    return (u + (u >> 12) * shift) & (kAggSlots - 1);
 }
 
 __device__ __forceinline__ void agg_clear(AggTable& t) {
@@ -117,8 +124,9 @@ __device__ __forceinline__ void agg_clear(AggTable& t) {
     }
 }
 
-__device__ __forceinline__ void agg_add(AggTable& t, int32_t n, double c, double* g) {
-    uint32_t h = agg_hash(n);
+__device__ __forceinline__ void agg_add(AggTable& t, int32_t n, double c, double* g,
+                                        uint32_t shift) {
+    uint32_t h = agg_hash(n, shift);
     for (int probe = 0; probe < kMaxProbe; ++probe) {
         const int32_t old = atomicCAS(&t.key[h], -1, n);
         if (old == -1 || old == n) {
@@ -151,6 +159,7 @@ struct TileArgs {
     double* v_out;         // per-element adjoints (M_*_V)
     double* gacc;          // FP64 accumulation target (atomic / colour modes)
     const int32_t* elist;  // element list (item -> element); nullptr: identity
+    uint32_t hash_shift;   // LDS table hash parameter (atomic modes)
 };
 
 // The element work of one workgroup: items first + i*blockDim + tid (i < EPT)
@@ -224,13 +233,14 @@ __device__ __forceinline__ double elem_tile(const TileArgs& a, int64_t first, in
         const double wd = ok[i] ? to_f64(wv[i]) : 0.0;
         if constexpr (has_obj(MODE)) tsum += wd * psi_from_sq(s2);
         if constexpr (has_rev(MODE)) v[i] = fb * wd * dpsi_from(s, s2);
-        if constexpr (MODE == M_HVP) {
+        if constexpr (MODE == M_HVP || MODE == M_JVP) {
             double q = 0.0;
             if (ok[i]) {
 #pragma unroll
                 for (int j = 0; j < K; ++j) q += to_f64(b[i][j]) * to_f64(XD[noff + c[i][j]]);
             }
-            v[i] = wd * ddpsi_from_sq(s2) * q;
+            if constexpr (MODE == M_HVP) v[i] = wd * ddpsi_from_sq(s2) * q;
+            if constexpr (MODE == M_JVP) tsum += wd * dpsi_from(s, s2) * q;
         }
     }
     // Phase 4: the reverse scatter.
@@ -248,7 +258,8 @@ __device__ __forceinline__ double elem_tile(const TileArgs& a, int64_t first, in
             if (ok[i]) {
 #pragma unroll
                 for (int j = 0; j < K; ++j)
-                    agg_add(*tab, (int32_t)(noff + c[i][j]), v[i] * to_f64(b[i][j]), a.gacc);
+                    agg_add(*tab, (int32_t)(noff + c[i][j]), v[i] * to_f64(b[i][j]), a.gacc,
+                            a.hash_shift);
             }
         __syncthreads();
         agg_flush(*tab, a.gacc);

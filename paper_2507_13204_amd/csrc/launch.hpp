@@ -20,7 +20,8 @@ enum MeshMode {
     M_ADJ_V = 4,        // v_e written out, no objective
     M_HVP = 5,          // c_e = w_e psi''(u_e) (G d)_e scattered with atomics
     M_GRAD_COLOUR = 6,  // primal + v_e scattered with plain read-add-write
-    M_ADJ_COLOUR = 7    // v_e scattered with plain read-add-write, no objective
+    M_ADJ_COLOUR = 7,   // v_e scattered with plain read-add-write, no objective
+    M_JVP = 8           // forward tangent: per-block sums of w_e psi'(u_e) (G d)_e
 };
 
 struct MeshView {
@@ -48,6 +49,7 @@ struct MeshPass {
     int block = 256;
     int ept = 1;
     int combine = 1;               // combine atomic contributions in LDS first
+    uint32_t hash_shift = 2533;    // LDS table hash parameter (see choose_hash_shift)
 };
 
 // Number of workgroups an element pass over n items launches.
@@ -99,7 +101,8 @@ struct BatchView {
     const void* B = nullptr;
     const void* w = nullptr;
     // Work list, one 32-byte record per tile in processing order:
-    // {first element, one past the last element, node offset of the instance,
+    // {first element, one past the last element,
+    //  (LDS hash shift << 40) | node offset of the instance,
     //  (instance << 40) | partial slot}.  Slots are laid out instance by
     // instance, so the segmented reduction sums each instance in order.
     const int64_t* tiles = nullptr;
@@ -123,6 +126,11 @@ struct BatchPass {
 
 hipError_t launch_batch_persistent(const BatchView& b, BatchMode mode, const BatchPass& p,
                                    hipStream_t s);
+
+// The LDS table hash parameter for a connectivity: `tiles` holds, per sampled
+// workgroup tile, the node numbers its elements touch (in element order);
+// returns the candidate shift with the fewest simulated probe steps.
+uint32_t choose_hash_shift(const int32_t* const* tiles, const int64_t* counts, int64_t n_tiles);
 
 // ------------------------------------------------------------------ dense
 

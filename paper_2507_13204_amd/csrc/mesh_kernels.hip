@@ -17,7 +17,6 @@
 #include <type_traits>
 
 #include "elem_tile.hpp"
-#include "persist.hpp"
 
 namespace pg {
 
@@ -33,12 +32,13 @@ k_mesh_elem(MeshView m, MeshPass p) {
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
     double fb = 1.0;
     if constexpr (has_rev(MODE)) fb = p.fbar ? p.fbar[0] : 1.0;
-    TileArgs a{m.conn, m.B, m.w, p.x, p.xd, p.u_in, p.u_store, p.v_out, p.gacc, p.elist};
+    TileArgs a{m.conn, m.B, m.w, p.x, p.xd, p.u_in, p.u_store, p.v_out, p.gacc, p.elist,
+               p.hash_shift};
     AggTable* tab = nullptr;
     if constexpr (AGG) tab = &agg;
     const double tsum = elem_tile<T, K, MODE, EPT, AGG>(a, (int64_t)lb * blockDim.x * EPT, n_items,
                                                         0, fb, tab);
-    if constexpr (has_obj(MODE)) {
+    if constexpr (has_sum(MODE)) {
         const double s = block_sum_dyn(tsum, lds);
         if (threadIdx.x == 0) p.partials[p.partial_base + lb] = s;
     }
@@ -75,10 +75,11 @@ k_mesh_elem_dyn(MeshView m, MeshPass p) {
         if constexpr (has_obj(MODE)) tsum = wd * psi_from_sq(s2);
         double v = 0.0;
         if constexpr (has_rev(MODE)) v = fb * wd * dpsi_from(u, s2);
-        if constexpr (MODE == M_HVP) {
+        if constexpr (MODE == M_HVP || MODE == M_JVP) {
             double q = 0.0;
             for (int j = 0; j < k; ++j) q += to_f64(B[e * k + j]) * to_f64(XD[conn[e * k + j]]);
-            v = wd * ddpsi_from_sq(s2) * q;
+            if constexpr (MODE == M_HVP) v = wd * ddpsi_from_sq(s2) * q;
+            if constexpr (MODE == M_JVP) tsum = wd * dpsi_from(u, s2) * q;
         }
         if constexpr (writes_v(MODE)) p.v_out[e] = v;
         if constexpr (is_atomic(MODE)) {
@@ -92,7 +93,7 @@ k_mesh_elem_dyn(MeshView m, MeshPass p) {
             }
         }
     }
-    if constexpr (has_obj(MODE)) {
+    if constexpr (has_sum(MODE)) {
         const double s = block_sum_dyn(tsum, lds);
         if (threadIdx.x == 0) p.partials[p.partial_base + lb] = s;
     }
@@ -304,17 +305,6 @@ hipError_t launch_elem_t(const MeshView& m, const MeshPass& p, hipStream_t s) {
     // Combine in LDS when the workgroup's contributions fit the table twice over
     // at worst (all distinct); meshes with locality fill it far less.
     const bool agg = is_atomic(MODE) && p.combine && (int64_t)p.block * EPT * K <= 2 * kAggSlots;
-    if constexpr ((MODE == M_GRAD_ATOMIC || MODE == M_ADJ_ATOMIC) && EPT == 1) {
-        if (agg && !p.elist) {
-            // Persistent pipelined pass: tile t is workgroup-sized, partial slot t.
-            MeshTiles tiles{m.n_elems, p.block, nb};
-            TileArgs a{m.conn, m.B, m.w, p.x, nullptr, p.u_in, nullptr, nullptr, p.gacc, nullptr};
-            auto kern = k_atomic_persistent<T, K, MODE, MeshTiles>;
-            hipLaunchKernelGGL(kern, dim3(resident_grid(kern, p.block, nb, 0)), dim3(p.block), 0, s,
-                               tiles, a, p.fbar, 0, p.partials + p.partial_base);
-            return hipGetLastError();
-        }
-    }
     if (agg)
         hipLaunchKernelGGL((k_mesh_elem<T, K, MODE, EPT, true>), dim3((unsigned)nb), dim3(p.block), 0,
                            s, m, p);
@@ -368,6 +358,7 @@ hipError_t launch_elem_mode(const MeshView& m, MeshMode mode, const MeshPass& p,
         case M_HVP: return launch_elem_k<T, M_HVP>(m, p, s);
         case M_GRAD_COLOUR: return launch_elem_k<T, M_GRAD_COLOUR>(m, p, s);
         case M_ADJ_COLOUR: return launch_elem_k<T, M_ADJ_COLOUR>(m, p, s);
+        case M_JVP: return launch_elem_k<T, M_JVP>(m, p, s);
     }
     return hipErrorInvalidValue;
 }

@@ -19,25 +19,29 @@ namespace pg {
 
 struct TileDesc {
     int64_t first, end, noff, slot, inst;
+    uint32_t shift;
 };
 
 // One mesh: tile t = elements [t*span, min(E, (t+1)*span)), partial slot t.
 struct MeshTiles {
     int64_t n_elems, span, n;
+    uint32_t shift;
     __device__ __forceinline__ TileDesc get(int64_t t) const {
         const int64_t f = t * span;
-        return TileDesc{f, f + span < n_elems ? f + span : n_elems, 0, t, 0};
+        return TileDesc{f, f + span < n_elems ? f + span : n_elems, 0, t, 0, shift};
     }
 };
 
-// A batch: packed records {first, end, node offset, (instance << 40) | slot}.
+// A batch: packed records {first, end, (hash shift << 40) | node offset,
+// (instance << 40) | slot}.
 struct BatchTiles {
     const int64_t* rec;
     int64_t n;
     __device__ __forceinline__ TileDesc get(int64_t t) const {
         const longlong2* p = reinterpret_cast<const longlong2*>(rec + 4 * t);
         const longlong2 a = p[0], b = p[1];
-        return TileDesc{a.x, a.y, b.x, b.y & ((1LL << 40) - 1), b.y >> 40};
+        constexpr int64_t lo = (1LL << 40) - 1;
+        return TileDesc{a.x, a.y, b.x & lo, b.y & lo, b.y >> 40, (uint32_t)(b.x >> 40)};
     }
 };
 
@@ -103,7 +107,7 @@ k_atomic_persistent(Tiles tiles, TileArgs a, const double* fbar, int fbar_per_in
         if (cur.ok) {
 #pragma unroll
             for (int j = 0; j < K; ++j)
-                agg_add(tab, (int32_t)(dc.noff + cur.c[j]), v * to_f64(cur.b[j]), a.gacc);
+                agg_add(tab, (int32_t)(dc.noff + cur.c[j]), v * to_f64(cur.b[j]), a.gacc, dc.shift);
         }
         __syncthreads();
         for (int s = threadIdx.x; s < kAggSlots; s += blockDim.x) {

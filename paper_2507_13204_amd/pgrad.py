@@ -32,7 +32,7 @@ CKPTS = {"recompute": RECOMPUTE, "store": STORE}
 
 EXPORTS = ("pg_default_options", "pg_mesh_plan", "pg_dense_plan", "pg_bdense_plan",
            "pg_mesh_batch_plan", "pg_workspace_size", "pg_bind_workspace", "pg_objective",
-           "pg_gradient", "pg_adjoint", "pg_hvp", "pg_timing", "pg_timing_read",
+           "pg_gradient", "pg_adjoint", "pg_hvp", "pg_jvp", "pg_timing", "pg_timing_read",
            "pg_laplace1d_plan", "pg_laplace1d_objective", "pg_laplace1d_gradient",
            "pg_plan_destroy", "pg_last_error", "pg_version")
 
@@ -86,6 +86,7 @@ def lib():
     L.pg_gradient.argtypes = [_VP, _VP, _VP, _VP, _VP]
     L.pg_adjoint.argtypes = [_VP, _VP, _VP, _VP, _VP]
     L.pg_hvp.argtypes = [_VP, _VP, _VP, _VP, _VP]
+    L.pg_jvp.argtypes = [_VP, _VP, _VP, _VP, _VP]
     L.pg_plan_destroy.argtypes = [_VP]
     L.pg_timing.argtypes = [_VP, _I32]
     L.pg_timing_read.argtypes = [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]
@@ -98,7 +99,7 @@ def lib():
     L.pg_version.argtypes = []
     for name in ("pg_mesh_plan", "pg_dense_plan", "pg_bdense_plan", "pg_mesh_batch_plan",
                  "pg_workspace_size", "pg_bind_workspace", "pg_objective", "pg_gradient",
-                 "pg_adjoint", "pg_hvp", "pg_timing", "pg_timing_read", "pg_plan_destroy",
+                 "pg_adjoint", "pg_hvp", "pg_jvp", "pg_timing", "pg_timing_read", "pg_plan_destroy",
                  "pg_laplace1d_plan", "pg_laplace1d_objective", "pg_laplace1d_gradient"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -249,6 +250,13 @@ class MeshObjective(_Plan):
         h = torch.empty_like(x) if out is None else out
         check(lib().pg_hvp(self._plan, _ptr(x), _ptr(v), _ptr(h), _stream(stream)), "pg_hvp")
         return h
+
+    def jvp(self, x, d, stream=None):
+        """Directional derivative f'(x) . d (forward tangent), a 0-d FP64 tensor."""
+        _need_cuda(x, d)
+        out = torch.empty((), dtype=torch.float64, device=x.device)
+        check(lib().pg_jvp(self._plan, _ptr(x), _ptr(d), _ptr(out), _stream(stream)), "pg_jvp")
+        return out
 
 
 class DenseObjective(_Plan):

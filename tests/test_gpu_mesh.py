@@ -126,6 +126,18 @@ def test_hvp_parity():
     assert rel(h, ref) <= TOL_F64_G
 
 
+@pytest.mark.parametrize("name", ["hex17", "rand_k5", "chain10k"])
+def test_jvp_parity(name):
+    """Forward tangent f'(x).d against the oracle gradient dotted with d."""
+    m = MESHES[name]()
+    d = inputs.fd_directions((m.n_nodes,), 1, seed=17)[0]
+    obj, x = _obj(m, "f64")
+    j = obj.jvp(x, to_dev(d)).item()
+    _, g = oracle.mesh_gradient(m.n_nodes, m.conn, m.B, m.w, m.x)
+    ref = float(g @ d)
+    assert abs(j - ref) <= TOL_F64_G * max(abs(ref), np.linalg.norm(g) * np.linalg.norm(d))
+
+
 def test_degenerate_meshes():
     from paper_2507_13204_amd import MeshObjective
     # no elements: f = 0, grad = 0
