@@ -206,6 +206,13 @@ def bench_hex(args):
                      "algorithmic_bytes": int(gbytes * 1e9)},
     }
 
+    # the other derivative modes on the same mesh (tangent and Hessian-vector product)
+    obj0, x0 = copies[0][0], copies[0][1]
+    dvec = torch.ones_like(x0)
+    hv = torch.empty_like(x0)
+    out["hvp_ms"] = round(_timed(lambda: obj0.hvp(x0, dvec, out=hv), 20, 3), 5)
+    out["jvp_ms"] = round(_timed(lambda: obj0.jvp(x0, dvec), 20, 3), 5)
+
     if not args.no_variants:
         variants = {}
         for adj in ("atomic", "gather", "colour"):
@@ -424,7 +431,30 @@ def bench_batch(args):
           roofline={"bound": "hbm", "achieved": round(gbytes / (k_ms * 1e-3), 2),
                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": round(gbytes / (k_ms * 1e-3) / PEAK_HBM_GBS, 4), "traffic": None,
-                    "kernel": "k_batch_persistent", "kernel_ms": round(k_ms, 5)})
+                    "kernel": "k_atomic_persistent (batch tiles)", "kernel_ms": round(k_ms, 5)},
+          cpu_baseline=_batch_cpu(bt, args.cpu_seconds))
+
+
+def _batch_cpu(bt, budget_s):
+    """The oracle on whole instances of the batch, in work-list order, until
+    the budget is spent; instances per second."""
+    import oracle
+    order = sorted(range(bt.n_inst), key=lambda i: -int(bt.inst[i][1]))
+    t0 = time.perf_counter()
+    done = 0
+    for i in order[::max(1, bt.n_inst // 32)]:
+        m = bt.instance(i)
+        oracle.mesh_gradient(m.n_nodes, m.conn, m.B, m.w, m.x)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    frac = sum(int(bt.inst[i][1]) for i in order[::max(1, bt.n_inst // 32)][:done]) / max(
+        1, int(bt.inst[:, 1].sum()))
+    return {"value": round(frac * bt.n_inst / el, 3), "unit": "instances/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{done} instances (every {max(1, bt.n_inst // 32)}th of the size-ordered list, "
+                      f"{100 * frac:.1f}% of the elements) in {el:.1f} s, scaled to the batch"}
 
 
 def bench_chain(args):
@@ -447,10 +477,24 @@ def bench_chain(args):
         sweep.append((n, round(ms_f * 1e3, 3), round(ms_g * 1e3, 3), round(ms_g / ms_f, 4)))
         obj.close()
     ratios = sorted(r[3] for r in sweep)
+    import oracle
+    m = inputs.chain(10_000)
+    reps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < 1.0:
+        oracle.mesh_gradient(m.n_nodes, m.conn, m.B, m.w, m.x)
+        reps += 1
+    cpu_us = (time.perf_counter() - t0) / reps * 1e6
+    nbytes = m.conn.nbytes + m.B.nbytes + m.w.nbytes + 2 * m.x.nbytes
     _line("1D chain gradient/objective wall-clock ratio (max over n = 100..10,000)", ratios[-1],
           "ratio", args, sweep[-1][2] / 1e3, "f64",
           {"workload": "1D chain, n = 100..10,000 (the paper's sweep of dim(x))"}, higher=False,
-          median_ratio=ratios[len(ratios) // 2], sweep_n_us_f_us_grad_ratio=sweep)
+          median_ratio=ratios[len(ratios) // 2], sweep_n_us_f_us_grad_ratio=sweep,
+          roofline={"bound": "hbm", "achieved": round(nbytes / (sweep[-1][2] * 1e-6) / 1e9, 3),
+                    "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(nbytes / (sweep[-1][2] * 1e-6) / 1e9 / PEAK_HBM_GBS, 6),
+                    "traffic": None, "kernel": "whole gradient call at n = 10,000 (launch-bound)"},
+          cpu_baseline={"value": round(cpu_us, 2), "unit": "us per gradient (n = 10,000)",
+                        "cores": 1, "kind": "oracle", "sample": f"{reps} oracle gradients"})
 
 
 # The paper's wall-clock times of f and of its generated gradient for dim(x) = 1
@@ -458,6 +502,20 @@ def bench_chain(args):
 PAPER_US = {"H100": {1: (41.79, 74.70), 10000: (47.82, 85.44)},
             "MI250X (one GCD)": {1: (89.67, 194.68), 10000: (113.62, 233.82)},
             "Ponte Vecchio": {1: (28.16, 56.07), 10000: (38.11, 68.24)}}
+
+
+def _paper_cpu():
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(10000)
+    x, b = rng.uniform(-1, 1, 10000), rng.uniform(-1, 1, 10000)
+    reps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < 1.0:
+        oracle.laplace1d_gradient(x, b)
+        reps += 1
+    us = (time.perf_counter() - t0) / reps * 1e6
+    return {"value": round(us, 2), "unit": "us per gradient (n = 10,000)", "cores": 1,
+            "kind": "oracle", "sample": f"{reps} oracle gradients in x and b"}
 
 
 def bench_paper(args):
@@ -488,7 +546,12 @@ def bench_paper(args):
           {"workload": "the paper's section 4 example, 1D Laplacian, dim(x) = 1, 100, ..., 10,000"},
           higher=False, median_ratio=r[len(r) // 2],
           atomic_schedule_max_ratio=max(v[3] for v in res["atomic"]),
-          paper_us_f_grad=PAPER_US, sweep_gather=res["gather"], sweep_atomic=res["atomic"])
+          paper_us_f_grad=PAPER_US, sweep_gather=res["gather"], sweep_atomic=res["atomic"],
+          roofline={"bound": "hbm", "achieved": round(32 * 10000 / (res["gather"][-1][2] * 1e-6) / 1e9, 3),
+                    "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(32 * 10000 / (res["gather"][-1][2] * 1e-6) / 1e9 / PEAK_HBM_GBS, 6),
+                    "traffic": None, "kernel": "whole gradient call at n = 10,000 (launch-bound)"},
+          cpu_baseline=_paper_cpu())
 
 
 def main():
