@@ -204,6 +204,82 @@ pg_status pg_hvp(pg_plan plan, const void* x, const void* v, void* hv, pg_stream
  * Mesh plans only; reduced in a fixed order. */
 pg_status pg_jvp(pg_plan plan, const void* x, const void* d, double* jvp_out, pg_stream stream);
 
+/* ----------------------------------------------------- composed programs */
+
+/* A program is a chain of data-parallel operations on 1D FP64 views ending in
+ * a parallel sum, differentiated by the library with the rules of section 3,
+ * one construct at a time:
+ *   - every view that depends on an input gets a shadow view of the same
+ *     size (section 3.1); views that depend on no input are inactive and get
+ *     none;
+ *   - reads become accumulations into the shadow and writes become reads of
+ *     it (section 3.1, view accesses), so the reverse pass runs the ops in
+ *     reverse order;
+ *   - the reverse of the final sum is a broadcast of the seed (section 3.2,
+ *     parallel_sum);
+ *   - nonlinear intermediates are recorded on a tape between kernels
+ *     (section 4), sized when the program is planned and bound once
+ *     (conclusion: size-deduced tape allocated outside the kernels);
+ *   - an accumulation whose index is itself a view entry (gather through a
+ *     connectivity table) races and uses atomic adds; one that reads through
+ *     several index expressions (a stencil) is rescheduled into a gather by
+ *     the written index, so it needs none (section 3.3; conclusion).
+ * Build a program with the pg_prog_* builders (view ids are returned in
+ * *view, in creation order), then plan, bind a workspace and run. */
+typedef struct pg_prog_s* pg_prog;
+typedef enum { PG_MAP_SQUARE = 0, PG_MAP_PSI = 1 } pg_map_fn;
+
+pg_status pg_prog_create(pg_prog* prog);
+/* Active input of n entries; its device pointer is given to pg_prog_run. */
+pg_status pg_prog_input(pg_prog prog, int64_t n, int32_t* view);
+/* Inactive operand of n entries (device pointer kept, not owned). */
+pg_status pg_prog_const(pg_prog prog, int64_t n, const double* data, int32_t* view);
+/* y = alpha * a */
+pg_status pg_prog_scale(pg_prog prog, int32_t a, double alpha, int32_t* view);
+/* y_i = sum_t coeffs[t] * a_{i + offsets[t]}, taps outside [0, n) dropped
+ * (offsets, coeffs: host arrays of n_taps entries, copied; n_taps <= 16). */
+pg_status pg_prog_stencil(pg_prog prog, int32_t a, int32_t n_taps, const int32_t* offsets,
+                          const double* coeffs, int32_t* view);
+/* y_e = sum_j B[e*k + j] * a[conn[e*k + j]] for e < n_elems (device conn and
+ * B kept, not owned; conn entries must lie in [0, length of a)). */
+pg_status pg_prog_gather(pg_prog prog, int32_t a, int64_t n_elems, int32_t k, const int32_t* conn,
+                         const double* B, int32_t* view);
+/* y = alpha * a + beta * b (equal lengths) */
+pg_status pg_prog_add(pg_prog prog, int32_t a, double alpha, int32_t b, double beta,
+                      int32_t* view);
+/* y = a (.) b (equal lengths) */
+pg_status pg_prog_mul(pg_prog prog, int32_t a, int32_t b, int32_t* view);
+/* y = fn(a) elementwise: PG_MAP_SQUARE (s^2) or PG_MAP_PSI (psi above) */
+pg_status pg_prog_map(pg_prog prog, int32_t a, pg_map_fn fn, int32_t* view);
+/* y_i = sum_{j <= i} a_j (inclusive prefix sum).  The reverse of a scan is
+ * the scan of the output shadow taken from the other end, abar_j +=
+ * sum_{i >= j} ybar_i: the rule the paper's conclusion lists as missing for
+ * parallel_scan.  Fixed summation order (deterministic). */
+pg_status pg_prog_scan(pg_prog prog, int32_t a, int32_t* view);
+/* f = sum of view a.  Ends the program. */
+pg_status pg_prog_sum(pg_prog prog, int32_t a);
+/* Checks the program, runs the activity analysis, lays out the tape and the
+ * shadows; *workspace_bytes (host out) is what pg_prog_bind_workspace needs. */
+pg_status pg_prog_plan(pg_prog prog, size_t* workspace_bytes);
+/* workspace: device memory of at least the planned bytes, 256-byte aligned,
+ * owned by the caller and used by every later run (tape, shadows, partials).
+ * Checks every gather's connectivity against its operand on the device, on the
+ * null stream, and waits for it (PG_ERANGE if an entry is out of range). */
+pg_status pg_prog_bind_workspace(pg_prog prog, void* workspace, size_t bytes);
+/* inputs: host array of device pointers, one per input in creation order.
+ * f_out: device FP64 (may be NULL).  grads: NULL (objective only) or a host
+ * array with one device pointer per input (NULL entries skipped); each is
+ * overwritten with df/d(input).  Enqueued on stream. */
+pg_status pg_prog_run(pg_prog prog, const double* const* inputs, double* f_out,
+                      double* const* grads, pg_stream stream);
+/* What the transformation produced (host out): kernel launches of the forward
+ * and reverse passes (shadow clearing not counted), reverse accumulations
+ * made atomic by the race rule,
+ * reverse accumulations rescheduled into gathers, and tape bytes. */
+pg_status pg_prog_info(pg_prog prog, int32_t* fwd_kernels, int32_t* rev_kernels,
+                       int32_t* atomic_ops, int32_t* rescheduled_ops, int64_t* tape_bytes);
+pg_status pg_prog_destroy(pg_prog prog);
+
 /* Measurement hook.  mode 0: off; 1: time the dominant kernel of every
  * subsequent evaluation (the element pass of a mesh or batch, the fused row
  * pass of a dense plan, the forward or backward product of a batched dense

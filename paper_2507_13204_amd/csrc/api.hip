@@ -28,6 +28,19 @@ pg_status fail(pg_status s, const char* fmt, ...) {
     return s;
 }
 
+}  // namespace
+
+namespace pg {
+// Shared with the other ABI translation units (composed programs).
+pg_status set_error(pg_status s, const char* msg) {
+    snprintf(g_err, sizeof g_err, "%s", msg);
+    return s;
+}
+void clear_error() { g_err[0] = 0; }
+}  // namespace pg
+
+namespace {
+
 #define PG_HIP(call)                                                                  \
     do {                                                                              \
         hipError_t e_ = (call);                                                       \

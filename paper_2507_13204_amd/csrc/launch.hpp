@@ -192,3 +192,47 @@ hipError_t launch_laplace1d(int64_t n, Dtype dt, int mode, const void* x, const 
                             double* partials, int accumulate, hipStream_t s);
 
 }  // namespace pg
+
+namespace pg {
+
+// ------------------------------------------------------- composed programs
+
+enum ProgKind { P_INPUT = 0, P_CONST = 1, P_SCALE, P_STENCIL, P_GATHER, P_ADD, P_MUL, P_MAP, P_SUM, P_SCAN };
+
+constexpr int kMaxTaps = 16;
+
+struct ProgTaps {
+    int32_t n = 0;
+    int32_t off[kMaxTaps] = {};
+    double coef[kMaxTaps] = {};
+};
+
+// One construct as the kernels see it.  Forward: y = op(a[, b]) over n
+// outputs (for P_SUM, y receives per-workgroup partials).  Reverse: the
+// shadows ab / bb (nullptr when the operand is inactive) accumulate the
+// adjoint of the output shadow yb (for P_SUM, the seed is alpha).  P_SCAN
+// uses scratch (prog_scan_chunks(n) doubles) for its chunk totals.
+struct ProgOpDev {
+    int kind = 0;
+    int64_t n = 0;
+    const double* a = nullptr;
+    const double* b = nullptr;
+    double* y = nullptr;
+    double alpha = 1.0, beta = 1.0;
+    int fn = 0;
+    ProgTaps taps;
+    int32_t k = 0;
+    const int32_t* conn = nullptr;
+    const double* B = nullptr;
+    const double* yb = nullptr;
+    double* ab = nullptr;
+    double* bb = nullptr;
+    double* scratch = nullptr;
+};
+
+hipError_t launch_prog_fwd(const ProgOpDev& o, hipStream_t s);
+hipError_t launch_prog_rev(const ProgOpDev& o, hipStream_t s);
+int64_t prog_sum_blocks(int64_t n);
+int64_t prog_scan_chunks(int64_t n);
+
+}  // namespace pg

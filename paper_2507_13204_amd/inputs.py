@@ -222,3 +222,76 @@ def uneven_batch(n_inst: int = 256, seed: int = SEED_BATCH, lo: int = 10, hi: in
     w = np.concatenate(ws) if ws else np.zeros(0)
     x = np.concatenate(xs) if xs else np.zeros(0)
     return MeshBatch(inst, 8, conn, B, w, x, s_arr)
+
+
+# ---------------------------------------------------------- composed programs
+#
+# A program is a list of constructs (tuples, view id = position in the list):
+# ("input", n), ("const", data), ("scale", a, alpha), ("stencil", a, offsets,
+# coeffs), ("gather", a, conn, B), ("add", a, alpha, b, beta), ("mul", a, b),
+# ("map", a, "square" | "psi"), ("scan", a), and last ("sum", a).
+
+@dataclasses.dataclass
+class ProgramCase:
+    spec: list
+    inputs: List[np.ndarray]
+    name: str
+
+
+def program_mesh(m: Mesh) -> ProgramCase:
+    """The element objective written as constructs: gather, map psi, weight, sum."""
+    spec = [("input", m.n_nodes), ("gather", 0, m.conn, m.B), ("map", 1, "psi"),
+            ("const", m.w), ("mul", 2, 3), ("sum", 4)]
+    return ProgramCase(spec, [m.x], "mesh-" + m.name)
+
+
+def program_paper(n: int, seed: int = SEED_CHAIN) -> ProgramCase:
+    """The section 4 example as constructs: scale by 3, the Dirichlet 1D
+    Laplacian stencil (-1, 2, -1), subtract b, square, sum; inputs x then b,
+    both ~ U(-1, 1)."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1.0, 1.0, n)
+    b = rng.uniform(-1.0, 1.0, n)
+    spec = [("input", n), ("input", n), ("scale", 0, 3.0),
+            ("stencil", 2, [-1, 0, 1], [-1.0, 2.0, -1.0]), ("add", 3, 1.0, 1, -1.0),
+            ("map", 4, "square"), ("sum", 5)]
+    return ProgramCase(spec, [x, b], f"paper{n}")
+
+
+def program_mix(n: int, n_elems: int, k: int, seed: int = 5, hot: int = 0) -> ProgramCase:
+    """Every construct at least once, with active and inactive branches, two
+    inputs, a self product and a gather whose reverse races.  hot > 0 draws
+    the gather's connectivity from only the first `hot` entries (many
+    colliding writes in the reverse pass)."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1.0, 1.0, n)
+    y = rng.uniform(-1.0, 1.0, n)
+    c = rng.uniform(-1.0, 1.0, n)
+    offs = [-2, -1, 0, 1, 3]
+    coef = list(rng.uniform(-0.6, 0.6, len(offs)))
+    top = hot if hot > 0 else max(n, 1)
+    conn = rng.integers(0, top, size=(n_elems, k)).astype(np.int32)
+    B = rng.standard_normal((n_elems, k)) / np.sqrt(k)
+    wE = rng.uniform(0.5, 1.5, n_elems)
+    spec = [
+        ("input", n),                        # 0 x
+        ("input", n),                        # 1 y
+        ("const", c),                        # 2 c (inactive)
+        ("stencil", 0, offs, coef),          # 3 active stencil: rescheduled reverse
+        ("scale", 1, -0.7),                  # 4
+        ("mul", 3, 4),                       # 5 both operands active
+        ("add", 5, 0.3, 2, 1.1),             # 6 one operand inactive
+        ("map", 6, "psi"),                   # 7
+        ("scan", 7),                         # 8 prefix sum: reverse suffix scan
+        ("scale", 8, 1.0 / max(n, 1)),       # 9
+        ("stencil", 2, [0, 1], [1.0, -1.0]), # 10 inactive stencil: no reverse
+        ("add", 9, 1.0, 10, 0.5),            # 11
+        ("gather", 11, conn, B),             # 12 gather: atomic reverse
+        ("mul", 12, 12),                     # 13 self product
+        ("map", 12, "square"),               # 14
+        ("add", 13, 0.25, 14, 0.75),         # 15
+        ("const", wE),                       # 16
+        ("mul", 15, 16),                     # 17
+        ("sum", 17),
+    ]
+    return ProgramCase(spec, [x, y], f"mix{n}x{n_elems}x{k}" + (f"hot{hot}" if hot else ""))

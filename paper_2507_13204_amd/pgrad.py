@@ -34,7 +34,12 @@ EXPORTS = ("pg_default_options", "pg_mesh_plan", "pg_dense_plan", "pg_bdense_pla
            "pg_mesh_batch_plan", "pg_workspace_size", "pg_bind_workspace", "pg_objective",
            "pg_gradient", "pg_adjoint", "pg_hvp", "pg_jvp", "pg_timing", "pg_timing_read",
            "pg_laplace1d_plan", "pg_laplace1d_objective", "pg_laplace1d_gradient",
-           "pg_plan_destroy", "pg_last_error", "pg_version")
+           "pg_plan_destroy", "pg_last_error", "pg_version",
+           "pg_prog_create", "pg_prog_input", "pg_prog_const", "pg_prog_scale", "pg_prog_stencil",
+           "pg_prog_gather", "pg_prog_add", "pg_prog_mul", "pg_prog_map", "pg_prog_scan",
+           "pg_prog_sum", "pg_prog_plan", "pg_prog_bind_workspace", "pg_prog_run", "pg_prog_info",
+           "pg_prog_destroy")
+MAPS = {"square": 0, "psi": 1}
 
 
 class PgError(RuntimeError):
@@ -93,6 +98,27 @@ def lib():
     L.pg_laplace1d_plan.argtypes = [_PLANP, _I64, ctypes.c_int, OP, _SZP]
     L.pg_laplace1d_objective.argtypes = [_VP, _VP, _VP, _VP, _VP]
     L.pg_laplace1d_gradient.argtypes = [_VP, _VP, _VP, _VP, _VP, _VP, _VP]
+    I32P = ctypes.POINTER(_I32)
+    D = ctypes.c_double
+    L.pg_prog_create.argtypes = [_PLANP]
+    L.pg_prog_input.argtypes = [_VP, _I64, I32P]
+    L.pg_prog_const.argtypes = [_VP, _I64, _VP, I32P]
+    L.pg_prog_scale.argtypes = [_VP, _I32, D, I32P]
+    L.pg_prog_stencil.argtypes = [_VP, _I32, _I32, I32P, ctypes.POINTER(D), I32P]
+    L.pg_prog_gather.argtypes = [_VP, _I32, _I64, _I32, _VP, _VP, I32P]
+    L.pg_prog_add.argtypes = [_VP, _I32, D, _I32, D, I32P]
+    L.pg_prog_mul.argtypes = [_VP, _I32, _I32, I32P]
+    L.pg_prog_map.argtypes = [_VP, _I32, ctypes.c_int, I32P]
+    L.pg_prog_scan.argtypes = [_VP, _I32, I32P]
+    L.pg_prog_sum.argtypes = [_VP, _I32]
+    L.pg_prog_plan.argtypes = [_VP, _SZP]
+    L.pg_prog_bind_workspace.argtypes = [_VP, _VP, ctypes.c_size_t]
+    L.pg_prog_run.argtypes = [_VP, ctypes.POINTER(_VP), _VP, ctypes.POINTER(_VP), _VP]
+    L.pg_prog_info.argtypes = [_VP, I32P, I32P, I32P, I32P, ctypes.POINTER(_I64)]
+    L.pg_prog_destroy.argtypes = [_VP]
+    for name in EXPORTS:
+        if name.startswith("pg_prog_"):
+            getattr(L, name).restype = ctypes.c_int
     L.pg_last_error.restype = ctypes.c_char_p
     L.pg_last_error.argtypes = []
     L.pg_version.restype = ctypes.c_int
@@ -391,6 +417,177 @@ class Laplace1D(_Plan):
         check(lib().pg_laplace1d_gradient(self._plan, _ptr(x), _ptr(b), _ptr(gx), _ptr(gb),
                                           _ptr(f), _stream(stream)), "pg_laplace1d_gradient")
         return f, gx, gb
+
+
+# ---------------------------------------------------------- composed programs
+
+class Program:
+    """A chain of data-parallel constructs ending in a sum, whose reverse pass
+    the library generates construct by construct (pg_prog_* in the C ABI).
+
+    Builders return view ids.  Device operands given to ``const`` and
+    ``gather`` are kept referenced by this object.  ``plan(device)`` runs the
+    activity analysis, lays out the tape and binds a workspace; ``run`` then
+    evaluates f and, when asked, the gradient with respect to every input.
+    """
+
+    def __init__(self):
+        self._p = ctypes.c_void_p()
+        check(lib().pg_prog_create(ctypes.byref(self._p)), "pg_prog_create")
+        self._keep = []
+        self._ws = None
+        self.n_inputs = 0
+        self.input_lengths = []
+        self.workspace_bytes = 0
+
+    @classmethod
+    def from_spec(cls, spec, device="cuda") -> "Program":
+        """Build (not plan) a program from construct tuples: ("input", n),
+        ("const", data), ("scale", a, alpha), ("stencil", a, offsets, coeffs),
+        ("gather", a, conn, B), ("add", a, alpha, b, beta), ("mul", a, b),
+        ("map", a, fn), ("scan", a), ("sum", a); array operands (NumPy or
+        torch) are copied to the device."""
+        p = cls()
+
+        def dev(a, dtype):
+            t = a if isinstance(a, torch.Tensor) else torch.from_numpy(a)
+            return t.to(device=device, dtype=dtype).contiguous()
+
+        for op in spec:
+            k = op[0]
+            if k == "input":
+                p.input(op[1])
+            elif k == "const":
+                p.const(dev(op[1], torch.float64))
+            elif k == "scale":
+                p.scale(op[1], op[2])
+            elif k == "stencil":
+                p.stencil(op[1], op[2], op[3])
+            elif k == "gather":
+                p.gather(op[1], dev(op[2], torch.int32), dev(op[3], torch.float64))
+            elif k == "add":
+                p.add(op[1], op[3], op[2], op[4])
+            elif k == "mul":
+                p.mul(op[1], op[2])
+            elif k == "map":
+                p.map(op[1], op[2])
+            elif k == "scan":
+                p.scan(op[1])
+            elif k == "sum":
+                p.sum(op[1])
+            else:
+                raise PgError(EINVAL, "from_spec", f"unknown construct {k!r}")
+        return p
+
+    def _view(self, fn, where, *args) -> int:
+        v = _I32()
+        check(fn(self._p, *args, ctypes.byref(v)), where)
+        return v.value
+
+    def input(self, n: int) -> int:
+        v = self._view(lib().pg_prog_input, "pg_prog_input", int(n))
+        self.n_inputs += 1
+        self.input_lengths.append(int(n))
+        return v
+
+    def const(self, data: torch.Tensor) -> int:
+        _need_cuda(data)
+        if data.dtype != torch.float64 or data.dim() != 1:
+            raise PgError(EDTYPE, "const", "constants are 1-D float64 tensors")
+        self._keep.append(data)
+        return self._view(lib().pg_prog_const, "pg_prog_const", data.numel(), _ptr(data))
+
+    def scale(self, a: int, alpha: float) -> int:
+        return self._view(lib().pg_prog_scale, "pg_prog_scale", int(a), float(alpha))
+
+    def stencil(self, a: int, offsets: Sequence[int], coeffs: Sequence[float]) -> int:
+        n = len(offsets)
+        if len(coeffs) != n:
+            raise PgError(EINVAL, "stencil", "offsets and coeffs differ in length")
+        off = (_I32 * max(n, 1))(*[int(o) for o in offsets])
+        cf = (ctypes.c_double * max(n, 1))(*[float(c) for c in coeffs])
+        return self._view(lib().pg_prog_stencil, "pg_prog_stencil", int(a), n, off, cf)
+
+    def gather(self, a: int, conn: torch.Tensor, B: torch.Tensor) -> int:
+        _need_cuda(conn, B)
+        if conn.dtype != torch.int32 or B.dtype != torch.float64 or conn.dim() != 2 \
+                or tuple(B.shape) != tuple(conn.shape):
+            raise PgError(EDTYPE, "gather", "conn: (E, k) int32, B: (E, k) float64")
+        self._keep += [conn, B]
+        return self._view(lib().pg_prog_gather, "pg_prog_gather", int(a), conn.shape[0],
+                          conn.shape[1], _ptr(conn), _ptr(B))
+
+    def add(self, a: int, b: int, alpha: float = 1.0, beta: float = 1.0) -> int:
+        return self._view(lib().pg_prog_add, "pg_prog_add", int(a), float(alpha), int(b),
+                          float(beta))
+
+    def mul(self, a: int, b: int) -> int:
+        return self._view(lib().pg_prog_mul, "pg_prog_mul", int(a), int(b))
+
+    def map(self, a: int, fn: str) -> int:
+        return self._view(lib().pg_prog_map, "pg_prog_map", int(a), MAPS[fn])
+
+    def scan(self, a: int) -> int:
+        return self._view(lib().pg_prog_scan, "pg_prog_scan", int(a))
+
+    def sum(self, a: int) -> None:
+        check(lib().pg_prog_sum(self._p, int(a)), "pg_prog_sum")
+
+    def plan(self, device="cuda") -> "Program":
+        sz = ctypes.c_size_t()
+        check(lib().pg_prog_plan(self._p, ctypes.byref(sz)), "pg_prog_plan")
+        self.workspace_bytes = sz.value
+        raw = torch.empty(sz.value + WORKSPACE_ALIGN, dtype=torch.uint8, device=device)
+        off = (-raw.data_ptr()) % WORKSPACE_ALIGN
+        self._ws_raw = raw
+        self._ws = raw[off:off + sz.value]
+        torch.cuda.synchronize(device)  # operands are complete before the connectivity check
+        check(lib().pg_prog_bind_workspace(self._p, ctypes.c_void_p(self._ws.data_ptr()),
+                                           sz.value), "pg_prog_bind_workspace")
+        return self
+
+    def info(self) -> dict:
+        f, r, a, q = _I32(), _I32(), _I32(), _I32()
+        t = _I64()
+        check(lib().pg_prog_info(self._p, ctypes.byref(f), ctypes.byref(r), ctypes.byref(a),
+                                 ctypes.byref(q), ctypes.byref(t)), "pg_prog_info")
+        return {"fwd_kernels": f.value, "rev_kernels": r.value, "atomic_ops": a.value,
+                "rescheduled_ops": q.value, "tape_bytes": t.value}
+
+    def run(self, inputs: Sequence[torch.Tensor], grads=True, stream=None, f_out=None):
+        """f (0-d float64 tensor) and, when grads is True (or a list of output
+        tensors / None entries), the gradients with respect to the inputs."""
+        if len(inputs) != self.n_inputs:
+            raise PgError(EINVAL, "run", f"expected {self.n_inputs} inputs")
+        for x, n in zip(inputs, self.input_lengths):
+            _need_cuda(x)
+            if x.dtype != torch.float64 or x.numel() != n:
+                raise PgError(EDTYPE, "run", "inputs are float64 tensors of the declared lengths")
+        dev = inputs[0].device if inputs else torch.device("cuda")
+        f = torch.empty((), dtype=torch.float64, device=dev) if f_out is None else f_out
+        ins = (_VP * max(self.n_inputs, 1))(*[x.data_ptr() for x in inputs])
+        outs = None
+        if grads is True:
+            outs = [torch.empty_like(x) for x in inputs]
+        elif grads:
+            outs = list(grads)
+            _need_cuda(*outs)
+        gp = None
+        if outs is not None:
+            gp = (_VP * max(self.n_inputs, 1))(*[None if g is None else g.data_ptr() for g in outs])
+        check(lib().pg_prog_run(self._p, ins, _ptr(f), gp, _stream(stream)), "pg_prog_run")
+        return (f, outs) if outs is not None else f
+
+    def close(self):
+        if self._p:
+            lib().pg_prog_destroy(self._p)
+            self._p = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------ autograd

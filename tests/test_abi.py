@@ -149,3 +149,84 @@ def test_timing_arguments():
     assert L.pg_timing(plan, 0) == P.OK
     assert L.pg_timing_read(plan, ctypes.byref(ms), ctypes.byref(n)) == P.OK and n.value == 0
     L.pg_plan_destroy(plan)
+
+
+# ---------------------------------------------------------- composed programs
+
+def _prog():
+    L = P.lib()
+    p = ctypes.c_void_p()
+    assert L.pg_prog_create(ctypes.byref(p)) == P.OK
+    return L, p
+
+
+def _v(fn, *args):
+    v = ctypes.c_int32(-1)
+    st = fn(*args, ctypes.byref(v))
+    return st, v.value
+
+
+def test_program_builders_check_their_arguments():
+    L, p = _prog()
+    st, x = _v(L.pg_prog_input, p, 100)
+    assert st == P.OK and x == 0
+    st, y = _v(L.pg_prog_input, p, 50)
+    assert st == P.OK and y == 1
+    assert _v(L.pg_prog_scale, p, 7, 1.0)[0] == P.EINVAL            # no such view
+    assert _v(L.pg_prog_add, p, x, 1.0, y, 1.0)[0] == P.EINVAL      # lengths differ
+    assert _v(L.pg_prog_mul, p, x, y)[0] == P.EINVAL
+    off = (ctypes.c_int32 * 17)(*range(17))
+    cf = (ctypes.c_double * 17)(*([1.0] * 17))
+    assert _v(L.pg_prog_stencil, p, x, 17, off, cf)[0] == P.EINVAL  # too many taps
+    assert _v(L.pg_prog_stencil, p, x, 0, off, cf)[0] == P.EINVAL
+    assert _v(L.pg_prog_map, p, x, 9)[0] == P.EINVAL                # unknown map
+    assert _v(L.pg_prog_gather, p, x, 10, 0, FAKE, FAKE)[0] == P.EINVAL   # k < 1
+    assert _v(L.pg_prog_gather, p, x, 10, 33, FAKE, FAKE)[0] == P.EINVAL  # k > 32
+    assert _v(L.pg_prog_gather, p, x, 10, 4, None, FAKE)[0] == P.EINVAL
+    assert _v(L.pg_prog_const, p, 5, None)[0] == P.EINVAL
+    assert L.pg_prog_plan(p, ctypes.byref(ctypes.c_size_t())) == P.ESTATE  # no sum yet
+    assert L.pg_prog_sum(p, x) == P.OK
+    assert L.pg_prog_sum(p, x) == P.ESTATE
+    assert _v(L.pg_prog_scale, p, x, 2.0)[0] == P.ESTATE            # program ended
+    L.pg_prog_destroy(p)
+
+
+def test_program_plan_reports_the_generated_reverse_pass():
+    """Host-only planning: activity analysis, race rule and tape size."""
+    L, p = _prog()
+    n, E, k = 1000, 300, 4
+    _, x = _v(L.pg_prog_input, p, n)
+    _, c = _v(L.pg_prog_const, p, n, FAKE)
+    off = (ctypes.c_int32 * 3)(-1, 0, 1)
+    cf = (ctypes.c_double * 3)(-1.0, 2.0, -1.0)
+    _, s1 = _v(L.pg_prog_stencil, p, x, 3, off, cf)       # active, 3 taps: rescheduled
+    _, s2 = _v(L.pg_prog_stencil, p, c, 3, off, cf)       # inactive: no reverse kernel
+    _, a = _v(L.pg_prog_add, p, s1, 1.0, s2, -1.0)
+    _, g = _v(L.pg_prog_gather, p, a, E, k, FAKE, FAKE)   # active gather: atomic
+    _, gc = _v(L.pg_prog_gather, p, c, E, k, FAKE, FAKE)  # inactive gather
+    _, m = _v(L.pg_prog_mul, p, g, gc)
+    _, sc = _v(L.pg_prog_scan, p, m)
+    _, q = _v(L.pg_prog_map, p, sc, 0)
+    assert L.pg_prog_sum(p, q) == P.OK
+    sz = ctypes.c_size_t()
+    assert L.pg_prog_plan(p, ctypes.byref(sz)) == P.OK
+    assert sz.value > 0 and sz.value % P.WORKSPACE_ALIGN == 0
+    f, r, at, rs = (ctypes.c_int32() for _ in range(4))
+    tape = ctypes.c_int64()
+    assert L.pg_prog_info(p, ctypes.byref(f), ctypes.byref(r), ctypes.byref(at),
+                          ctypes.byref(rs), ctypes.byref(tape)) == P.OK
+    # forward: 7 one-launch constructs + the scan's 3 + the sum's 2
+    assert f.value == 7 + 3 + 2
+    # reverse: s1, a, g, m, q (one launch each), the scan (3), the seed broadcast
+    assert r.value == 5 + 3 + 1
+    assert at.value == 1 and rs.value == 1
+    assert tape.value == 8 * (3 * n + 5 * E)  # every intermediate view is recorded
+    # workspace holds at least the tape and the active shadows
+    assert sz.value >= tape.value + 8 * (2 * n + 4 * E)
+    # binding checks size and alignment before any device work
+    assert L.pg_prog_bind_workspace(p, None, sz.value) == P.EWORKSPACE
+    assert L.pg_prog_bind_workspace(p, FAKE + 8, sz.value) == P.EWORKSPACE
+    assert L.pg_prog_bind_workspace(p, FAKE, sz.value - 1) == P.EWORKSPACE
+    ins = (ctypes.c_void_p * 1)(FAKE)
+    assert L.pg_prog_run(p, ins, None, None, None) == P.ESTATE       # no workspace bound
+    L.pg_prog_destroy(p)
