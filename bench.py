@@ -54,8 +54,9 @@ def parse():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=6.0)
     ap.add_argument("--workload", default="hex",
-                    choices=["hex", "dense", "bdense", "batch", "chain", "paper"],
-                    help="hex (default, the headline), dense, bdense, batch, chain, paper")
+                    choices=["hex", "dense", "bdense", "batch", "chain", "paper", "program"],
+                    help="hex (default, the headline), dense, bdense, batch, chain, paper, "
+                         "program")
     ap.add_argument("--dense-n", type=int, default=10_000)
     ap.add_argument("--bd-m", type=int, default=4096)
     ap.add_argument("--bd-n", type=int, default=1024)
@@ -554,6 +555,72 @@ def bench_paper(args):
           cpu_baseline=_paper_cpu())
 
 
+def _program_cpu(budget_s: float = 5.0):
+    """The program oracle (forward Jacobian accumulation) on hex meshes of
+    growing side until the budget is spent; rate in algorithmic GB/s."""
+    from oracle import program as OP
+    from paper_2507_13204_amd import inputs
+    m = inputs.hex_mesh(64, seed=1)
+    case = inputs.program_mesh(m)
+    done_bytes, t0, runs = 0, time.perf_counter(), 0
+    while time.perf_counter() - t0 < budget_s:
+        OP.gradient(case.spec, case.inputs)
+        done_bytes += algorithmic_bytes(m.n_nodes, m.n_elems, 8, 8, True)
+        runs += 1
+    dt = time.perf_counter() - t0
+    return {"value": round(done_bytes / dt / 1e9, 5), "unit": "GB/s (algorithmic)", "cores": 1,
+            "kind": "oracle", "sample": f"{runs} program-oracle gradients of the 64^3 hex mesh "
+            "(forward Jacobians in scipy.sparse)"}
+
+
+def bench_program(args):
+    """Composed programs (pg_prog_*): the 128^3 hex objective written as
+    constructs (gather, map psi, weight, sum) against the fused element
+    kernel, and the paper's example at dim(x) = 10,000 against its hand-fused
+    form.  The difference is what fusing the constructs buys."""
+    import torch
+    from paper_2507_13204_amd import Laplace1D, MeshObjective, Program, inputs
+    dev = torch.device("cuda:0")
+    m = inputs.hex_mesh(args.side)
+    case = inputs.program_mesh(m)
+    prog = Program.from_spec(case.spec, device=dev).plan(dev)
+    x = torch.from_numpy(m.x).to(dev)
+    f = torch.empty((), dtype=torch.float64, device=dev)
+    g = [torch.empty_like(x)]
+    ms_prog = _timed(lambda: prog.run([x], grads=g, f_out=f), args.steps, args.warmup)
+    ms_prog_f = _timed(lambda: prog.run([x], grads=None, f_out=f), args.steps, args.warmup)
+    info = prog.info()
+    del prog
+    mo = MeshObjective(torch.from_numpy(m.conn).to(dev), torch.from_numpy(m.B).to(dev),
+                       torch.from_numpy(m.w).to(dev), m.n_nodes)
+    gf = torch.empty_like(x)
+    ms_fused = _timed(lambda: mo.gradient(x, out=gf, f_out=f), args.steps, args.warmup)
+    mo.close()
+    pc = inputs.program_paper(10000, seed=10000)
+    pp = Program.from_spec(pc.spec, device=dev).plan(dev)
+    xs = [torch.from_numpy(v).to(dev) for v in pc.inputs]
+    gp = [torch.empty_like(v) for v in xs]
+    ms_pp = _timed(lambda: pp.run(xs, grads=gp, f_out=f), args.steps, args.warmup)
+    lp = Laplace1D(10000)
+    ms_lp = _timed(lambda: lp.gradient(xs[0], xs[1], gx=gp[0], gb=gp[1], f_out=f), args.steps,
+                   args.warmup)
+    lp.close()
+    alg = algorithmic_bytes(m.n_nodes, m.n_elems, 8, 8, True)
+    gbs = alg / (ms_prog * 1e-3) / 1e9
+    _line(f"composed-program gradient throughput, {args.side}^3 hex mesh (algorithmic bytes)",
+          gbs, "GB/s", args, ms_prog, "f64",
+          {"workload": f"hex mesh {args.side}^3 nodes as constructs gather -> map psi -> "
+                       "weight -> sum, FP64, reverse pass generated construct by construct"},
+          program_objective_ms=round(ms_prog_f, 5), fused_gradient_ms=round(ms_fused, 5),
+          program_over_fused=round(ms_prog / ms_fused, 3), program_info=info,
+          paper_example_program_us=round(ms_pp * 1e3, 2),
+          paper_example_fused_us=round(ms_lp * 1e3, 2),
+          roofline={"bound": "hbm", "achieved": round(gbs, 3), "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 6), "traffic": None,
+                    "kernel": "whole program gradient call (one kernel per construct)"},
+          cpu_baseline=None if args.no_cpu else _program_cpu())
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -566,7 +633,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     {"hex": bench_hex, "dense": bench_dense, "bdense": bench_bdense, "batch": bench_batch,
-     "chain": bench_chain, "paper": bench_paper}[args.workload](args)
+     "chain": bench_chain, "paper": bench_paper, "program": bench_program}[args.workload](args)
 
 
 if __name__ == "__main__":

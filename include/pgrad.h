@@ -217,9 +217,14 @@ pg_status pg_jvp(pg_plan plan, const void* x, const void* d, double* jvp_out, pg
  *     reverse order;
  *   - the reverse of the final sum is a broadcast of the seed (section 3.2,
  *     parallel_sum);
- *   - nonlinear intermediates are recorded on a tape between kernels
- *     (section 4), sized when the program is planned and bound once
- *     (conclusion: size-deduced tape allocated outside the kernels);
+ *   - only what feeds the sum runs; a shadow's first delivery in the
+ *     reverse pass stores and later ones add, so shadows need no clearing
+ *     except where atomics deliver;
+ *   - forward values the reverse pass reads are recorded on a tape between
+ *     kernels (section 4) or recomputed inside a fused group (see
+ *     pg_prog_fusion); the tape is sized when the program is planned and
+ *     bound once (conclusion: size-deduced tape allocated outside the
+ *     kernels);
  *   - an accumulation whose index is itself a view entry (gather through a
  *     connectivity table) races and uses atomic adds; one that reads through
  *     several index expressions (a stencil) is rescheduled into a gather by
@@ -272,12 +277,31 @@ pg_status pg_prog_bind_workspace(pg_prog prog, void* workspace, size_t bytes);
  * overwritten with df/d(input).  Enqueued on stream. */
 pg_status pg_prog_run(pg_prog prog, const double* const* inputs, double* f_out,
                       double* const* grads, pg_stream stream);
-/* What the transformation produced (host out): kernel launches of the forward
- * and reverse passes (shadow clearing not counted), reverse accumulations
- * made atomic by the race rule,
- * reverse accumulations rescheduled into gathers, and tape bytes. */
-pg_status pg_prog_info(pg_prog prog, int32_t* fwd_kernels, int32_t* rev_kernels,
-                       int32_t* atomic_ops, int32_t* rescheduled_ops, int64_t* tape_bytes);
+/* What the transformation produced (filled by pg_prog_info, host out). */
+typedef struct {
+    int32_t fwd_kernels;      /* launches of the forward pass (shadow clearing not counted) */
+    int32_t rev_kernels;      /* launches of the reverse pass */
+    int32_t atomic_ops;       /* reverse deliveries made atomic by the race rule (gathers) */
+    int32_t rescheduled_ops;  /* reverse stencils rescheduled into gathers (no atomics) */
+    int32_t groups;           /* fused groups of pointwise constructs (the sum's included) */
+    int32_t fused_gathers;    /* gathers evaluated inside their consuming group */
+    int32_t dead_ops;         /* constructs that do not feed the sum (never run) */
+    int64_t tape_bytes;       /* forward values recorded between kernels */
+    int64_t workspace_bytes;
+} pg_prog_stats;
+
+/* Fusion level, before pg_prog_plan.  1 (default): chains of pointwise
+ * constructs (scale, add, mul, map) run as one kernel per group, keep their
+ * intermediates in registers and recompute them in the reverse pass (no
+ * tape); a gather read only by one group runs inside it, its reverse being
+ * an LDS-combined atomic scatter; the group holding the sum runs its
+ * forward and reverse in one pass (the seed of f is the constant 1).  The
+ * conclusion of the paper names kernel fusion and recomputation as ways to
+ * cut the cost of the generated gradient.  0: one kernel per construct each
+ * way (the sum's partials are taken by the kernel producing the summed
+ * view), every value another construct reads recorded. */
+pg_status pg_prog_fusion(pg_prog prog, int32_t level);
+pg_status pg_prog_info(pg_prog prog, pg_prog_stats* stats);
 pg_status pg_prog_destroy(pg_prog prog);
 
 /* Measurement hook.  mode 0: off; 1: time the dominant kernel of every

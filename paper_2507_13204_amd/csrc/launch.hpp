@@ -207,32 +207,73 @@ struct ProgTaps {
     double coef[kMaxTaps] = {};
 };
 
-// One construct as the kernels see it.  Forward: y = op(a[, b]) over n
-// outputs (for P_SUM, y receives per-workgroup partials).  Reverse: the
-// shadows ab / bb (nullptr when the operand is inactive) accumulate the
-// adjoint of the output shadow yb (for P_SUM, the seed is alpha).  P_SCAN
-// uses scratch (prog_scan_chunks(n) doubles) for its chunk totals.
+// One non-pointwise construct (stencil, gather, scan) as its kernels see it.
+// Forward: y = op(a).  Reverse: ab receives the adjoint of the output shadow
+// yb, stored (accumulate 0) or added (accumulate 1); the gather's reverse is
+// always an atomic addition.  The scan uses scratch (prog_scan_chunks(n)
+// doubles) for its chunk totals.
 struct ProgOpDev {
     int kind = 0;
     int64_t n = 0;
     const double* a = nullptr;
-    const double* b = nullptr;
     double* y = nullptr;
-    double alpha = 1.0, beta = 1.0;
-    int fn = 0;
     ProgTaps taps;
     int32_t k = 0;
     const int32_t* conn = nullptr;
     const double* B = nullptr;
     const double* yb = nullptr;
     double* ab = nullptr;
-    double* bb = nullptr;
+    int accumulate = 1;
     double* scratch = nullptr;
 };
 
 hipError_t launch_prog_fwd(const ProgOpDev& o, hipStream_t s);
 hipError_t launch_prog_rev(const ProgOpDev& o, hipStream_t s);
-int64_t prog_sum_blocks(int64_t n);
 int64_t prog_scan_chunks(int64_t n);
+
+// A fused group: a chain of pointwise constructs (scale, add, mul, map) over
+// one index range, evaluated per entry in registers.  Slots 0..n_leaves-1
+// hold the leaves (views read from outside the group, or the output of one
+// fused gather); op j writes slot n_leaves + j.  Forward: exported slots are
+// written to memory and the summed slot is reduced into per-workgroup
+// partials.  Reverse: the forward slots are recomputed from the leaves, the
+// adjoints start from the export shadows and the seed of the sum, run
+// through the ops in reverse order, and leave through the leaf shadows
+// (stored or added) and, for a fused gather, through an LDS-combined atomic
+// scatter into the gather operand's shadow.
+constexpr int kGSlots = 16, kGLeaves = 8, kGOps = 12, kGExports = 8;
+
+struct GOp {
+    int32_t kind = 0, a = 0, b = 0, fn = 0;
+    double alpha = 1.0, beta = 1.0;
+};
+
+struct GroupDev {
+    int64_t n = 0;
+    int32_t n_leaves = 0, n_ops = 0, n_exports = 0;
+    int32_t sum_slot = -1;
+    int32_t gather_slot = -1;
+    int32_t gk = 0;
+    const int32_t* gconn = nullptr;
+    const double* gB = nullptr;
+    const double* gsrc = nullptr;
+    double* gsrc_shadow = nullptr;
+    uint32_t hash_shift = 2533;
+    double seed = 1.0;
+    const double* leaf[kGLeaves] = {};
+    double* leaf_shadow[kGLeaves] = {};
+    int32_t leaf_acc[kGLeaves] = {};
+    GOp ops[kGOps];
+    int32_t export_slot[kGExports] = {};
+    double* export_val[kGExports] = {};
+    const double* export_shadow[kGExports] = {};
+    double* partials = nullptr;
+};
+
+enum GroupMode { G_FWD = 0, G_REV = 1, G_FWDREV = 2 };
+
+hipError_t launch_group(const GroupDev& g, int mode, hipStream_t s);
+int64_t group_blocks(int64_t n);
+constexpr int kGroupBlock = 256;
 
 }  // namespace pg

@@ -52,10 +52,35 @@ struct Op {
     const double* data = nullptr;  // P_CONST
     int32_t input_index = -1;      // P_INPUT
     // plan
-    bool active = false;
+    bool live = false;       // feeds the summed view
+    bool active = false;     // depends on an input
+    int32_t group = -1;      // fused group holding this pointwise construct
+    bool fused = false;      // a gather evaluated inside its consuming group
+    bool stored = false;     // forward value materialised
+    bool exported = false;   // group member read from outside its group
     size_t val_off = NONE;   // forward value in the workspace (intermediates)
     size_t shd_off = NONE;   // shadow in the workspace (active intermediates)
 };
+
+bool pointwise(int kind) { return kind == P_SCALE || kind == P_ADD || kind == P_MUL || kind == P_MAP; }
+
+struct Group {
+    std::vector<int32_t> members, leaves;
+    int32_t gather = -1;  // fused gather view (one of the leaves)
+    bool sealed = false, has_sum = false;
+    int32_t pos = 0;      // schedule position: its last member (the end for a sum-only group)
+    uint32_t hash_shift = 2533;
+};
+
+// One step of the forward schedule: a non-pointwise construct or a group.
+struct Item {
+    bool group;
+    int32_t id;
+    int32_t pos;
+};
+
+// How a reverse step delivers into an operand's shadow.
+enum Deliver { D_STORE = 0, D_ADD = 1, D_ATOMIC = 2 };
 
 }  // namespace
 
@@ -63,13 +88,19 @@ struct pg_prog_s {
     std::vector<Op> ops;  // one per view, in creation order (view id = index)
     int32_t sum_view = -1;
     int32_t n_inputs = 0;
+    int32_t fusion = 1;
     bool planned = false;
+    std::vector<Group> groups;
+    std::vector<Item> sched;                       // forward order
+    int32_t sum_group = -1;
+    std::vector<int32_t> zero_views;               // shadows cleared before the reverse pass
+    std::vector<int32_t> op_acc;                   // per view: delivery of a construct's reverse
+    std::vector<std::vector<int32_t>> leaf_acc;    // per group, per leaf
     size_t ws_bytes = 0, partials_off = NONE, fscratch_off = NONE, flag_off = NONE, scan_off = NONE;
     int64_t tape_bytes = 0;
     std::vector<size_t> input_shadow_off;  // internal shadows for inputs without a grad buffer
     char* ws = nullptr;
-    // info
-    int32_t fwd_kernels = 0, rev_kernels = 0, atomic_ops = 0, rescheduled_ops = 0;
+    pg_prog_stats stats{};
 };
 
 namespace {
@@ -246,15 +277,225 @@ pg_status pg_prog_sum(pg_prog p, int32_t a) {
     return PG_OK;
 }
 
+pg_status pg_prog_fusion(pg_prog p, int32_t level) {
+    clear_error();
+    if (!p) return perr(PG_EINVAL, "program is NULL");
+    if (level != 0 && level != 1) return perr(PG_EINVAL, "fusion level must be 0 or 1");
+    p->fusion = level;
+    p->planned = false;
+    return PG_OK;
+}
+
 pg_status pg_prog_plan(pg_prog p, size_t* workspace_bytes) {
     clear_error();
     if (!p || !workspace_bytes) return perr(PG_EINVAL, "NULL argument");
     if (p->sum_view < 0) return perr(PG_ESTATE, "the program has no pg_prog_sum");
-    // Activity: a view is active if it is an input or reads an active view.
-    for (Op& op : p->ops) {
-        op.active = op.kind == P_INPUT ||
-                    (op.a >= 0 && p->ops[op.a].active) || (op.b >= 0 && p->ops[op.b].active);
+    std::vector<Op>& ops = p->ops;
+    const int32_t nv = (int32_t)ops.size(), S = p->sum_view;
+    // Liveness: only what feeds the summed view runs.
+    for (Op& op : ops) {
+        op.live = false;
+        op.group = -1;
+        op.fused = op.stored = op.exported = false;
+        op.val_off = op.shd_off = NONE;
     }
+    ops[(size_t)S].live = true;
+    for (int32_t v = S; v >= 0; --v) {
+        if (!ops[(size_t)v].live) continue;
+        if (ops[(size_t)v].a >= 0) ops[(size_t)ops[(size_t)v].a].live = true;
+        if (ops[(size_t)v].b >= 0) ops[(size_t)ops[(size_t)v].b].live = true;
+    }
+    // Activity: a view is active if it is an input or reads an active view.
+    for (Op& op : ops)
+        op.active = op.kind == P_INPUT || (op.a >= 0 && ops[(size_t)op.a].active) ||
+                    (op.b >= 0 && ops[(size_t)op.b].active);
+
+    // Fused groups of pointwise constructs.  A group runs where its last
+    // member is; once a construct outside it reads a member, it is sealed
+    // (it must run before that reader) and takes no further members.
+    std::vector<Group>& G = p->groups;
+    G.clear();
+    auto add_leaf = [&](Group& g, int32_t u) {
+        if (std::find(g.leaves.begin(), g.leaves.end(), u) == g.leaves.end()) g.leaves.push_back(u);
+    };
+    auto read_member = [&](int32_t u, int32_t reader_group) {
+        const int32_t gu = ops[(size_t)u].group;
+        if (gu >= 0 && gu != reader_group) {
+            G[(size_t)gu].sealed = true;
+            ops[(size_t)u].exported = true;
+        }
+    };
+    auto leaves_after = [&](const std::vector<int32_t>& gs, int32_t v) {
+        // leaves of the union of groups gs plus construct v
+        std::vector<int32_t> mem, lv;
+        for (int32_t gi : gs) mem.insert(mem.end(), G[(size_t)gi].members.begin(), G[(size_t)gi].members.end());
+        mem.push_back(v);
+        auto add = [&](int32_t u) {
+            if (u < 0 || std::find(mem.begin(), mem.end(), u) != mem.end()) return;
+            if (std::find(lv.begin(), lv.end(), u) == lv.end()) lv.push_back(u);
+        };
+        for (int32_t gi : gs)
+            for (int32_t u : G[(size_t)gi].leaves) add(u);
+        add(ops[(size_t)v].a);
+        add(ops[(size_t)v].b);
+        return std::make_pair(mem.size(), lv.size());
+    };
+    for (int32_t v = 0; v < nv; ++v) {
+        Op& op = ops[(size_t)v];
+        if (!op.live || op.kind == P_INPUT || op.kind == P_CONST) continue;
+        if (!pointwise(op.kind)) {
+            read_member(op.a, -1);
+            continue;
+        }
+        std::vector<int32_t> cand;
+        if (p->fusion) {
+            for (int32_t u : {op.a, op.b}) {
+                if (u < 0) continue;
+                const int32_t gu = ops[(size_t)u].group;
+                if (gu >= 0 && !G[(size_t)gu].sealed &&
+                    std::find(cand.begin(), cand.end(), gu) == cand.end())
+                    cand.push_back(gu);
+            }
+            auto fits = [&](const std::vector<int32_t>& gs) {
+                const auto ml = leaves_after(gs, v);
+                return (int)ml.first <= kGOps && (int)ml.second <= kGLeaves &&
+                       (int)(ml.first + ml.second) <= kGSlots;
+            };
+            if (!cand.empty() && !fits(cand)) {
+                std::vector<int32_t> one;
+                for (int32_t gi : cand)
+                    if (fits({gi})) {
+                        one.push_back(gi);
+                        break;
+                    }
+                cand = one;
+            }
+        }
+        int32_t gi;
+        if (cand.empty()) {
+            gi = (int32_t)G.size();
+            G.emplace_back();
+        } else {
+            gi = cand[0];
+            for (size_t c = 1; c < cand.size(); ++c) {  // merge into the first
+                Group& src = G[(size_t)cand[c]];
+                for (int32_t m : src.members) ops[(size_t)m].group = gi;
+                G[(size_t)gi].members.insert(G[(size_t)gi].members.end(), src.members.begin(), src.members.end());
+                for (int32_t u : src.leaves) add_leaf(G[(size_t)gi], u);
+                src.members.clear();
+                src.leaves.clear();
+            }
+        }
+        Group& g = G[(size_t)gi];
+        g.members.push_back(v);
+        op.group = gi;
+        std::sort(g.members.begin(), g.members.end());
+        // leaves: operands outside the group (drop any that became members)
+        std::vector<int32_t> lv;
+        for (int32_t u : g.leaves)
+            if (ops[(size_t)u].group != gi) lv.push_back(u);
+        g.leaves = lv;
+        for (int32_t u : {op.a, op.b}) {
+            if (u < 0) continue;
+            read_member(u, gi);
+            if (ops[(size_t)u].group != gi) add_leaf(g, u);
+        }
+    }
+    // The sum joins the group holding the summed view, else a group of its own.
+    if (ops[(size_t)S].group >= 0) {
+        p->sum_group = ops[(size_t)S].group;
+    } else {
+        p->sum_group = (int32_t)G.size();
+        G.emplace_back();
+        G.back().leaves.push_back(S);
+        G.back().pos = nv;
+    }
+    G[(size_t)p->sum_group].has_sum = true;
+    // Gathers read only by one group (as a leaf) run inside it, unless that
+    // group also reads the gather's operand (its shadow would then take a
+    // plain store and atomics in one kernel).
+    if (p->fusion) {
+        std::vector<int32_t> readers((size_t)nv, 0), reader_group((size_t)nv, -1);
+        for (int32_t v = 0; v < nv; ++v) {
+            const Op& op = ops[(size_t)v];
+            if (!op.live || op.kind == P_INPUT || op.kind == P_CONST || pointwise(op.kind)) continue;
+            readers[(size_t)op.a]++;
+        }
+        for (size_t gi = 0; gi < G.size(); ++gi)
+            for (int32_t u : G[gi].leaves) {
+                readers[(size_t)u]++;
+                reader_group[(size_t)u] = (int32_t)gi;
+            }
+        for (int32_t v = 0; v < nv; ++v) {
+            Op& op = ops[(size_t)v];
+            if (!op.live || op.kind != P_GATHER || readers[(size_t)v] != 1 || reader_group[(size_t)v] < 0)
+                continue;
+            Group& g = G[(size_t)reader_group[(size_t)v]];
+            if (g.gather >= 0 || std::find(g.leaves.begin(), g.leaves.end(), op.a) != g.leaves.end())
+                continue;
+            g.gather = v;
+            op.fused = true;
+        }
+    }
+    // Forward schedule.
+    p->sched.clear();
+    for (size_t gi = 0; gi < G.size(); ++gi) {
+        Group& g = G[gi];
+        if (g.members.empty() && !g.has_sum) continue;  // merged away
+        if (!g.members.empty()) g.pos = g.members.back();
+        p->sched.push_back(Item{true, (int32_t)gi, g.pos});
+    }
+    for (int32_t v = 0; v < nv; ++v) {
+        const Op& op = ops[(size_t)v];
+        if (op.live && !op.fused && (op.kind == P_STENCIL || op.kind == P_GATHER || op.kind == P_SCAN))
+            p->sched.push_back(Item{false, v, v});
+    }
+    std::sort(p->sched.begin(), p->sched.end(),
+              [](const Item& x, const Item& y) { return x.pos < y.pos; });
+    // Materialised views: outputs of stand-alone constructs and group exports.
+    for (Op& op : ops) {
+        if (!op.live || op.kind == P_INPUT || op.kind == P_CONST || op.fused) continue;
+        op.stored = !pointwise(op.kind) || op.exported;
+    }
+    // Reverse deliveries: walk the reverse schedule; a shadow's first
+    // delivery stores, later ones add; an atomic delivery needs a cleared
+    // shadow.  The sum group runs first (fused with its forward when asked).
+    p->op_acc.assign((size_t)nv, D_ADD);
+    p->leaf_acc.assign(G.size(), {});
+    p->zero_views.clear();
+    std::vector<char> touched((size_t)nv, 0);
+    auto deliver = [&](int32_t v, bool atomic) -> int32_t {
+        if (!ops[(size_t)v].active) return D_ADD;
+        if (atomic) {
+            if (!touched[(size_t)v]) p->zero_views.push_back(v);
+            touched[(size_t)v] = 1;
+            return D_ATOMIC;
+        }
+        const int32_t d = touched[(size_t)v] ? D_ADD : D_STORE;
+        touched[(size_t)v] = 1;
+        return d;
+    };
+    for (size_t r = p->sched.size(); r-- > 0;) {
+        const Item& it = p->sched[r];
+        if (it.group) {
+            Group& g = G[(size_t)it.id];
+            std::vector<int32_t>& la = p->leaf_acc[(size_t)it.id];
+            la.assign(g.leaves.size(), D_ADD);
+            for (size_t l = 0; l < g.leaves.size(); ++l) {
+                if (g.leaves[l] == g.gather) continue;
+                la[l] = deliver(g.leaves[l], false);
+            }
+            if (g.gather >= 0) deliver(ops[(size_t)g.gather].a, true);
+        } else {
+            const Op& op = ops[(size_t)it.id];
+            if (!op.active) continue;
+            p->op_acc[(size_t)it.id] = deliver(op.a, op.kind == P_GATHER);
+        }
+    }
+    for (int32_t v = 0; v < nv; ++v)
+        if (ops[(size_t)v].kind == P_INPUT && !touched[(size_t)v]) p->zero_views.push_back(v);
+
+    // Workspace layout.
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -262,42 +503,55 @@ pg_status pg_prog_plan(pg_prog p, size_t* workspace_bytes) {
         return o;
     };
     p->tape_bytes = 0;
-    for (Op& op : p->ops) {
-        op.val_off = op.shd_off = NONE;
-        if (op.kind == P_INPUT || op.kind == P_CONST) continue;
-        op.val_off = take(sizeof(double) * (size_t)op.n);  // recorded between kernels
+    for (Op& op : ops) {
+        if (!op.stored) continue;
+        op.val_off = take(sizeof(double) * (size_t)op.n);
         p->tape_bytes += (int64_t)(sizeof(double) * (size_t)op.n);
         if (op.active) op.shd_off = take(sizeof(double) * (size_t)op.n);
     }
     p->input_shadow_off.assign((size_t)p->n_inputs, NONE);
-    for (const Op& op : p->ops)
+    for (const Op& op : ops)
         if (op.kind == P_INPUT)
             p->input_shadow_off[(size_t)op.input_index] = take(sizeof(double) * (size_t)op.n);
-    const int64_t ns = p->ops[(size_t)p->sum_view].n;
-    p->partials_off = take(sizeof(double) * (size_t)std::max<int64_t>(prog_sum_blocks(ns), 1));
+    p->partials_off = take(sizeof(double) * (size_t)std::max<int64_t>(group_blocks(ops[(size_t)S].n), 1));
     p->fscratch_off = take(sizeof(double));
     p->flag_off = take(sizeof(int32_t) * 4);
     int64_t scan_chunks = 0;  // one totals buffer, reused by every scan in turn
-    for (const Op& op : p->ops)
-        if (op.kind == P_SCAN) scan_chunks = std::max(scan_chunks, prog_scan_chunks(op.n));
+    for (const Op& op : ops)
+        if (op.live && op.kind == P_SCAN) scan_chunks = std::max(scan_chunks, prog_scan_chunks(op.n));
     p->scan_off = scan_chunks ? take(sizeof(double) * (size_t)scan_chunks) : NONE;
     p->ws_bytes = off;
-    // What the transformation generates.
-    p->fwd_kernels = 0;
-    p->rev_kernels = 0;
-    p->atomic_ops = 0;
-    p->rescheduled_ops = 0;
-    for (const Op& op : p->ops) {
-        if (op.kind == P_INPUT || op.kind == P_CONST) continue;
-        const int32_t nk = op.kind == P_SCAN ? 3 : 1;  // a scan is three launches each way
-        p->fwd_kernels += nk;
-        if (!op.active) continue;
-        p->rev_kernels += nk;
-        if (op.kind == P_GATHER && p->ops[op.a].active) ++p->atomic_ops;
-        if (op.kind == P_STENCIL && op.taps.n > 1 && p->ops[op.a].active) ++p->rescheduled_ops;
+
+    // What the transformation produced.
+    pg_prog_stats& st = p->stats;
+    st = pg_prog_stats{};
+    for (const Item& it : p->sched) {
+        if (it.group) {
+            const Group& g = G[(size_t)it.id];
+            ++st.groups;
+            ++st.fwd_kernels;
+            bool rev = g.gather >= 0 && ops[(size_t)ops[(size_t)g.gather].a].active;
+            for (int32_t u : g.leaves) rev = rev || (u != g.gather && ops[(size_t)u].active);
+            if (rev && !(p->fusion && g.has_sum)) ++st.rev_kernels;
+            if (g.gather >= 0) {
+                ++st.fused_gathers;
+                if (ops[(size_t)ops[(size_t)g.gather].a].active) ++st.atomic_ops;
+            }
+        } else {
+            const Op& op = ops[(size_t)it.id];
+            const int32_t nk = op.kind == P_SCAN ? 3 : 1;  // a scan is three launches each way
+            st.fwd_kernels += nk;
+            if (!op.active) continue;
+            st.rev_kernels += nk;
+            if (op.kind == P_GATHER) ++st.atomic_ops;
+            if (op.kind == P_STENCIL && op.taps.n > 1) ++st.rescheduled_ops;
+        }
     }
-    p->fwd_kernels += 2;  // the sum's partials and its final fixed-order reduction
-    if (p->ops[(size_t)p->sum_view].active) ++p->rev_kernels;  // broadcast of the seed
+    st.fwd_kernels += 1;  // the fixed-order reduction of the sum's partials
+    for (const Op& op : ops)
+        if (!op.live && op.kind != P_INPUT && op.kind != P_CONST) ++st.dead_ops;
+    st.tape_bytes = p->tape_bytes;
+    st.workspace_bytes = (int64_t)p->ws_bytes;
     p->planned = true;
     p->ws = nullptr;
     *workspace_bytes = p->ws_bytes;
@@ -320,6 +574,29 @@ pg_status pg_prog_bind_workspace(pg_prog p, void* ws, size_t bytes) {
     int32_t hflag = 0;
     PG_HIP(hipMemcpy(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost));
     if (hflag) return perr(PG_ERANGE, "a gather's connectivity has an entry outside its operand");
+    // LDS hash rotation of each fused gather's scatter, chosen on sampled workgroups.
+    for (Group& g : p->groups) {
+        if (g.gather < 0) continue;
+        const Op& op = p->ops[(size_t)g.gather];
+        const int64_t span = kGroupBlock, nt = (op.n + span - 1) / span;
+        const int64_t ns = std::min<int64_t>(nt, 24);
+        std::vector<std::vector<int32_t>> tiles;
+        for (int64_t q = 0; q < ns; ++q) {
+            const int64_t t = nt > 1 ? q * (nt - 1) / std::max<int64_t>(ns - 1, 1) : 0;
+            const int64_t e0 = t * span, e1 = std::min(op.n, e0 + span);
+            tiles.emplace_back((size_t)((e1 - e0) * op.k));
+            if (tiles.back().empty()) continue;
+            PG_HIP(hipMemcpy(tiles.back().data(), op.conn + e0 * op.k,
+                             sizeof(int32_t) * tiles.back().size(), hipMemcpyDeviceToHost));
+        }
+        std::vector<const int32_t*> ptr;
+        std::vector<int64_t> cnt;
+        for (const auto& t : tiles) {
+            ptr.push_back(t.data());
+            cnt.push_back((int64_t)t.size());
+        }
+        g.hash_shift = tiles.empty() ? 2533u : choose_hash_shift(ptr.data(), cnt.data(), (int64_t)tiles.size());
+    }
     p->ws = static_cast<char*>(ws);
     return PG_OK;
 }
@@ -331,12 +608,13 @@ pg_status pg_prog_run(pg_prog p, const double* const* inputs, double* f_out, dou
     if (!p->planned || !p->ws) return perr(PG_ESTATE, "plan the program and bind a workspace first");
     if (p->n_inputs > 0 && !inputs) return perr(PG_EINVAL, "inputs is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const std::vector<Op>& ops = p->ops;
+    const size_t nv = ops.size();
     // Device pointers of every view's forward value and shadow.
-    const size_t nv = p->ops.size();
     std::vector<const double*> val(nv, nullptr);
     std::vector<double*> shd(nv, nullptr);
     for (size_t v = 0; v < nv; ++v) {
-        const Op& op = p->ops[v];
+        const Op& op = ops[v];
         if (op.kind == P_INPUT) {
             val[v] = inputs[op.input_index];
             if (op.n > 0 && !val[v]) return perr(PG_EINVAL, "input %d is NULL", op.input_index);
@@ -349,87 +627,120 @@ pg_status pg_prog_run(pg_prog p, const double* const* inputs, double* f_out, dou
             shd[v] = at(p, op.shd_off);
         }
     }
-    // Forward pass: one kernel per construct, outputs recorded on the tape.
-    for (size_t v = 0; v < nv; ++v) {
-        const Op& op = p->ops[v];
-        if (op.kind == P_INPUT || op.kind == P_CONST) continue;
-        ProgOpDev d;
-        d.kind = op.kind;
-        d.n = op.n;
-        d.a = val[(size_t)op.a];
-        d.b = op.b >= 0 ? val[(size_t)op.b] : nullptr;
-        d.y = at(p, op.val_off);
-        d.alpha = op.alpha;
-        d.beta = op.beta;
-        d.fn = op.fn;
-        d.taps = op.taps;
-        d.k = op.k;
-        d.conn = op.conn;
-        d.B = op.B;
-        d.scratch = at(p, p->scan_off);
-        PG_HIP(launch_prog_fwd(d, s));
-    }
-    const Op& so = p->ops[(size_t)p->sum_view];
+    const bool rev = grads != nullptr;
     double* partials = at(p, p->partials_off);
-    double* fdst = f_out ? f_out : at(p, p->fscratch_off);
-    {
-        ProgOpDev d;
-        d.kind = P_SUM;
-        d.n = so.n;
-        d.a = val[(size_t)p->sum_view];
-        d.y = partials;
-        PG_HIP(launch_prog_fwd(d, s));
-        PG_HIP(launch_final_sum(partials, prog_sum_blocks(so.n), fdst, s));
-    }
-    if (!grads) return PG_OK;
-    // Shadows start at zero; requested input gradients are the input shadows.
-    for (size_t v = 0; v < nv; ++v)
-        if (shd[v] && p->ops[v].active) PG_HIP(launch_zero(shd[v], sizeof(double) * (size_t)p->ops[v].n, s));
-    // Reverse of the sum: broadcast the seed 1 into the summed view's shadow.
-    if (so.active) {
-        ProgOpDev d;
-        d.kind = P_SUM;
-        d.n = so.n;
-        d.alpha = 1.0;
-        d.ab = shd[(size_t)p->sum_view];
-        PG_HIP(launch_prog_rev(d, s));
-    }
-    // Reverse pass: constructs in reverse order, reads turned into accumulations.
-    for (size_t r = nv; r-- > 0;) {
-        const Op& op = p->ops[r];
-        if (op.kind == P_INPUT || op.kind == P_CONST || !op.active) continue;
+    double* scratch = at(p, p->scan_off);
+    const int64_t n_sum = ops[(size_t)p->sum_view].n;
+
+    auto group_dev = [&](int32_t gi) {
+        const Group& g = p->groups[(size_t)gi];
+        GroupDev d;
+        d.n = g.members.empty() ? ops[(size_t)g.leaves[0]].n : ops[(size_t)g.members[0]].n;
+        d.n_leaves = (int32_t)g.leaves.size();
+        d.n_ops = (int32_t)g.members.size();
+        auto slot = [&](int32_t u) -> int32_t {
+            for (size_t l = 0; l < g.leaves.size(); ++l)
+                if (g.leaves[l] == u) return (int32_t)l;
+            for (size_t m = 0; m < g.members.size(); ++m)
+                if (g.members[m] == u) return (int32_t)(g.leaves.size() + m);
+            return -1;
+        };
+        for (size_t l = 0; l < g.leaves.size(); ++l) {
+            const int32_t u = g.leaves[l];
+            if (u == g.gather) continue;
+            d.leaf[l] = val[(size_t)u];
+            d.leaf_shadow[l] = ops[(size_t)u].active ? shd[(size_t)u] : nullptr;
+            d.leaf_acc[l] = p->leaf_acc[(size_t)gi][l] == D_ADD;
+        }
+        for (size_t m = 0; m < g.members.size(); ++m) {
+            const Op& op = ops[(size_t)g.members[m]];
+            GOp& o = d.ops[m];
+            o.kind = op.kind;
+            o.a = slot(op.a);
+            o.b = op.b >= 0 ? slot(op.b) : 0;
+            o.fn = op.fn;
+            o.alpha = op.alpha;
+            o.beta = op.beta;
+            if (op.exported) {
+                d.export_slot[d.n_exports] = (int32_t)(g.leaves.size() + m);
+                d.export_val[d.n_exports] = at(p, op.val_off);
+                d.export_shadow[d.n_exports] = op.active ? shd[(size_t)g.members[m]] : nullptr;
+                ++d.n_exports;
+            }
+        }
+        if (g.has_sum) {
+            d.sum_slot = slot(p->sum_view);
+            d.partials = partials;
+        }
+        if (g.gather >= 0) {
+            const Op& go = ops[(size_t)g.gather];
+            d.gather_slot = slot(g.gather);
+            d.gk = go.k;
+            d.gconn = go.conn;
+            d.gB = go.B;
+            d.gsrc = val[(size_t)go.a];
+            d.gsrc_shadow = ops[(size_t)go.a].active ? shd[(size_t)go.a] : nullptr;
+            d.hash_shift = g.hash_shift;
+        }
+        return d;
+    };
+    auto op_dev = [&](int32_t v) {
+        const Op& op = ops[(size_t)v];
         ProgOpDev d;
         d.kind = op.kind;
         d.n = op.n;
         d.a = val[(size_t)op.a];
-        d.b = op.b >= 0 ? val[(size_t)op.b] : nullptr;
-        d.alpha = op.alpha;
-        d.beta = op.beta;
-        d.fn = op.fn;
+        d.y = at(p, op.val_off);
         d.taps = op.taps;
         d.k = op.k;
         d.conn = op.conn;
         d.B = op.B;
-        d.yb = shd[r];
-        d.ab = p->ops[(size_t)op.a].active ? shd[(size_t)op.a] : nullptr;
-        d.bb = (op.b >= 0 && p->ops[(size_t)op.b].active) ? shd[(size_t)op.b] : nullptr;
-        d.scratch = at(p, p->scan_off);
-        if (!d.ab && !d.bb) continue;
-        PG_HIP(launch_prog_rev(d, s));
+        d.yb = shd[(size_t)v];
+        d.ab = ops[(size_t)op.a].active ? shd[(size_t)op.a] : nullptr;
+        d.accumulate = p->op_acc[(size_t)v] != D_STORE;
+        d.scratch = scratch;
+        return d;
+    };
+
+    // Shadows that take atomic additions (and gradients nothing reaches) start at zero.
+    if (rev)
+        for (int32_t v : p->zero_views)
+            PG_HIP(launch_zero(shd[(size_t)v], sizeof(double) * (size_t)ops[(size_t)v].n, s));
+    // Forward pass; with fusion the sum group runs its reverse in the same pass.
+    const bool fused_last = rev && p->fusion;
+    for (const Item& it : p->sched) {
+        if (it.group) {
+            const int mode = (it.id == p->sum_group && fused_last) ? G_FWDREV : G_FWD;
+            PG_HIP(launch_group(group_dev(it.id), mode, s));
+        } else {
+            PG_HIP(launch_prog_fwd(op_dev(it.id), s));
+        }
+    }
+    PG_HIP(launch_final_sum(partials, group_blocks(n_sum), f_out ? f_out : at(p, p->fscratch_off), s));
+    if (!rev) return PG_OK;
+    // Reverse pass: the schedule backwards, reads turned into deliveries.
+    for (size_t r = p->sched.size(); r-- > 0;) {
+        const Item& it = p->sched[r];
+        if (it.group) {
+            if (it.id == p->sum_group && fused_last) continue;
+            const GroupDev d = group_dev(it.id);
+            bool any = d.gsrc_shadow != nullptr;
+            for (int l = 0; l < d.n_leaves; ++l) any = any || d.leaf_shadow[l] != nullptr;
+            if (any) PG_HIP(launch_group(d, G_REV, s));
+        } else {
+            const Op& op = ops[(size_t)it.id];
+            if (!op.active) continue;
+            PG_HIP(launch_prog_rev(op_dev(it.id), s));
+        }
     }
     return PG_OK;
 }
 
-pg_status pg_prog_info(pg_prog p, int32_t* fwd_kernels, int32_t* rev_kernels, int32_t* atomic_ops,
-                       int32_t* rescheduled_ops, int64_t* tape_bytes) {
+pg_status pg_prog_info(pg_prog p, pg_prog_stats* stats) {
     clear_error();
-    if (!p) return perr(PG_EINVAL, "program is NULL");
+    if (!p || !stats) return perr(PG_EINVAL, "NULL argument");
     if (!p->planned) return perr(PG_ESTATE, "call pg_prog_plan first");
-    if (fwd_kernels) *fwd_kernels = p->fwd_kernels;
-    if (rev_kernels) *rev_kernels = p->rev_kernels;
-    if (atomic_ops) *atomic_ops = p->atomic_ops;
-    if (rescheduled_ops) *rescheduled_ops = p->rescheduled_ops;
-    if (tape_bytes) *tape_bytes = p->tape_bytes;
+    *stats = p->stats;
     return PG_OK;
 }
 

@@ -1,8 +1,11 @@
-// Kernels of composed programs: one data-parallel kernel per construct in the
-// forward pass (its output view is the tape entry the reverse pass reads), and
-// the generated adjoint of each construct in the reverse pass.  Shadows are
-// FP64 and accumulate with +=, as in the generated code of section 4.
+// Kernels of composed programs.  Non-pointwise constructs (stencil, gather,
+// scan) run one kernel each way; chains of pointwise constructs run as fused
+// groups (k_group), which recompute their forward values in registers in the
+// reverse pass instead of reading them from a tape.  Shadows are FP64; a
+// shadow's first contribution in the reverse pass stores, later ones add
+// (the generated code of section 4 zeroes every shadow and adds).
 #include "device_common.hpp"
+#include "elem_tile.hpp"
 #include "launch.hpp"
 
 namespace pg {
@@ -18,12 +21,6 @@ __device__ __forceinline__ double map_f(int fn, double s) {
 }
 __device__ __forceinline__ double map_df(int fn, double s) {
     return fn == 0 ? 2.0 * s : dpsi_from(s, s * s);
-}
-
-__global__ void __launch_bounds__(kBS)
-k_scale(int64_t n, const double* __restrict__ a, double alpha, double* __restrict__ y) {
-    const int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x;
-    if (i < n) y[i] = alpha * a[i];
 }
 
 __global__ void __launch_bounds__(kBS)
@@ -48,47 +45,13 @@ k_gather(int64_t E, int32_t k, const int32_t* __restrict__ conn, const double* _
     y[e] = s;
 }
 
-__global__ void __launch_bounds__(kBS)
-k_add(int64_t n, const double* __restrict__ a, double alpha, const double* __restrict__ b,
-      double beta, double* __restrict__ y) {
-    const int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x;
-    if (i < n) y[i] = alpha * a[i] + beta * b[i];
-}
-
-__global__ void __launch_bounds__(kBS)
-k_mul(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
-      double* __restrict__ y) {
-    const int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x;
-    if (i < n) y[i] = a[i] * b[i];
-}
-
-__global__ void __launch_bounds__(kBS)
-k_map(int64_t n, const double* __restrict__ a, int fn, double* __restrict__ y) {
-    const int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x;
-    if (i < n) y[i] = map_f(fn, a[i]);
-}
-
-__global__ void __launch_bounds__(kBS)
-k_sum(int64_t n, const double* __restrict__ a, double* __restrict__ partials) {
-    __shared__ double lds[kBS / kWave];
-    const int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x;
-    const double s = block_sum<kBS>(i < n ? a[i] : 0.0, lds);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
-
 // ---------------------------------------------------------- reverse pass
-
-// abar += alpha * ybar
-__global__ void __launch_bounds__(kBS)
-k_r_scale(int64_t n, const double* __restrict__ yb, double alpha, double* __restrict__ ab) {
-    const int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x;
-    if (i < n) ab[i] += alpha * yb[i];
-}
 
 // The reverse of a stencil reads ybar through several index expressions; it
 // is rescheduled by the written index: abar_j += sum_t c_t ybar_{j - o_t}.
 __global__ void __launch_bounds__(kBS)
-k_r_stencil(int64_t n, const double* __restrict__ yb, ProgTaps taps, double* __restrict__ ab) {
+k_r_stencil(int64_t n, const double* __restrict__ yb, ProgTaps taps, double* __restrict__ ab,
+            int accumulate) {
     const int64_t j = (int64_t)blockIdx.x * kBS + threadIdx.x;
     if (j >= n) return;
     double s = 0.0;
@@ -96,7 +59,10 @@ k_r_stencil(int64_t n, const double* __restrict__ yb, ProgTaps taps, double* __r
         const int64_t i = j - taps.off[t];
         if (i >= 0 && i < n) s += taps.coef[t] * yb[i];
     }
-    ab[j] += s;
+    if (accumulate)
+        ab[j] += s;
+    else
+        ab[j] = s;
 }
 
 // The reverse of a gather writes through an index that is a view entry: atomic.
@@ -107,44 +73,6 @@ k_r_gather(int64_t E, int32_t k, const int32_t* __restrict__ conn, const double*
     if (e >= E) return;
     const double v = yb[e];
     for (int j = 0; j < k; ++j) atomic_add_f64(ab + conn[e * k + j], B[e * k + j] * v);
-}
-
-// abar += alpha ybar, bbar += beta ybar (either may be absent; a == b allowed:
-// the same thread does both updates in order).
-__global__ void __launch_bounds__(kBS)
-k_r_add(int64_t n, const double* __restrict__ yb, double alpha, double* ab, double beta,
-        double* bb) {
-    const int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x;
-    if (i >= n) return;
-    const double v = yb[i];
-    if (ab) ab[i] += alpha * v;
-    if (bb) bb[i] += beta * v;
-}
-
-// abar += b ybar, bbar += a ybar (a and b are the stored forward values).
-__global__ void __launch_bounds__(kBS)
-k_r_mul(int64_t n, const double* __restrict__ yb, const double* a, const double* b, double* ab,
-        double* bb) {
-    const int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x;
-    if (i >= n) return;
-    const double v = yb[i], av = a[i], bv = b[i];
-    if (ab) ab[i] += bv * v;
-    if (bb) bb[i] += av * v;
-}
-
-// abar += fn'(a) ybar (a is the stored forward value).
-__global__ void __launch_bounds__(kBS)
-k_r_map(int64_t n, const double* __restrict__ yb, const double* __restrict__ a, int fn,
-        double* __restrict__ ab) {
-    const int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x;
-    if (i < n) ab[i] += map_df(fn, a[i]) * yb[i];
-}
-
-// The reverse of the sum: broadcast the seed, abar += fbar.
-__global__ void __launch_bounds__(kBS)
-k_r_sum(int64_t n, double fbar, double* __restrict__ ab) {
-    const int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x;
-    if (i < n) ab[i] += fbar;
 }
 
 // ------------------------------------------------------------ prefix scan
@@ -248,18 +176,210 @@ hipError_t launch_scan(int64_t n, const double* a, int rev, double* scratch, dou
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ fused groups
+
+// Sixteen FP64 slots addressed by a wave-uniform index.  A private array
+// indexed at run time would live in scratch memory; named members selected
+// by a switch on a uniform index stay in VGPRs and cost scalar branches only.
+#define PG_SLOTS(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
+struct Slots {
+#define PG_DECL(i) double r##i = 0.0;
+    PG_SLOTS(PG_DECL)
+#undef PG_DECL
+    __device__ __forceinline__ double get(int i) const {
+        switch (i) {
+#define PG_GET(i) case i: return r##i;
+            PG_SLOTS(PG_GET)
+#undef PG_GET
+        }
+        return 0.0;
+    }
+    __device__ __forceinline__ void set(int i, double v) {
+        switch (i) {
+#define PG_SET(i) case i: r##i = v; break;
+            PG_SLOTS(PG_SET)
+#undef PG_SET
+        }
+    }
+    __device__ __forceinline__ void add(int i, double v) {
+        switch (i) {
+#define PG_ADD(i) case i: r##i += v; break;
+            PG_SLOTS(PG_ADD)
+#undef PG_ADD
+        }
+    }
+};
+#undef PG_SLOTS
+static_assert(kGSlots == 16, "Slots holds sixteen values");
+
+// Row of the fused gather: K > 0 keeps it in registers (vector loads);
+// K < 0 is the generic row length, read again in the reverse scatter.
+template <int K>
+struct GatherRow {
+    static constexpr int N = K > 0 ? K : 1;
+    int32_t c[N];
+    double b[N];
+};
+
+template <int K>
+__device__ __forceinline__ double gather_value(const GroupDev& g, int64_t i, GatherRow<K>& row) {
+    double u = 0.0;
+    if constexpr (K > 0) {
+        load_conn_row<double, K>(g.gconn, i, row.c);
+        load_b_row<K>(g.gB, i, row.b);
+        double xv[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) xv[j] = g.gsrc[row.c[j]];
+#pragma unroll
+        for (int j = 0; j < K; ++j) u += row.b[j] * xv[j];
+    } else {
+        for (int j = 0; j < g.gk; ++j) u += g.gB[i * g.gk + j] * g.gsrc[g.gconn[i * g.gk + j]];
+    }
+    return u;
+}
+
+template <int K, int MODE>
+__global__ void __launch_bounds__(kGroupBlock) k_group(GroupDev g) {
+    constexpr bool REV = MODE != G_FWD;
+    constexpr bool FWD = MODE != G_REV;
+    constexpr bool AGG = REV && K != 0;
+    __shared__ double lds[kGroupBlock / kWave];
+    __shared__ typename std::conditional<AGG, AggTable, int>::type tab;
+    const bool scatter = AGG && g.gsrc_shadow != nullptr;
+    if constexpr (AGG) {
+        if (scatter) {
+            agg_clear(tab);
+            __syncthreads();
+        }
+    }
+    const int64_t i = xcd_remap(blockIdx.x, gridDim.x) * kGroupBlock + threadIdx.x;
+    const bool ok = i < g.n;
+    const int L = g.n_leaves;
+    Slots r;
+    GatherRow<K> row;
+    if (ok) {
+        for (int l = 0; l < L; ++l) {
+            if constexpr (K != 0) {
+                if (l == g.gather_slot) {
+                    r.set(l, gather_value<K>(g, i, row));
+                    continue;
+                }
+            }
+            r.set(l, g.leaf[l][i]);
+        }
+        for (int j = 0; j < g.n_ops; ++j) {
+            const GOp o = g.ops[j];
+            const double x = r.get(o.a);
+            double v;
+            switch (o.kind) {
+                case P_SCALE: v = o.alpha * x; break;
+                case P_ADD: v = o.alpha * x + o.beta * r.get(o.b); break;
+                case P_MUL: v = x * r.get(o.b); break;
+                default: v = map_f(o.fn, x); break;
+            }
+            r.set(L + j, v);
+        }
+        if constexpr (FWD) {
+            for (int x = 0; x < g.n_exports; ++x) g.export_val[x][i] = r.get(g.export_slot[x]);
+        }
+    }
+    if constexpr (FWD) {
+        if (g.sum_slot >= 0) {
+            const double t = block_sum<kGroupBlock>(ok ? r.get(g.sum_slot) : 0.0, lds);
+            if (threadIdx.x == 0) g.partials[blockIdx.x] = t;
+        }
+    }
+    if constexpr (REV) {
+        Slots a;
+        if (ok) {
+            if (g.sum_slot >= 0) a.add(g.sum_slot, g.seed);
+            for (int x = 0; x < g.n_exports; ++x)
+                if (g.export_shadow[x]) a.add(g.export_slot[x], g.export_shadow[x][i]);
+            for (int j = g.n_ops - 1; j >= 0; --j) {
+                const GOp o = g.ops[j];
+                const double yb = a.get(L + j);
+                switch (o.kind) {
+                    case P_SCALE: a.add(o.a, o.alpha * yb); break;
+                    case P_ADD:
+                        a.add(o.a, o.alpha * yb);
+                        a.add(o.b, o.beta * yb);
+                        break;
+                    case P_MUL: {
+                        const double av = r.get(o.a), bv = r.get(o.b);
+                        a.add(o.a, bv * yb);
+                        a.add(o.b, av * yb);
+                        break;
+                    }
+                    default: a.add(o.a, map_df(o.fn, r.get(o.a)) * yb); break;
+                }
+            }
+            for (int l = 0; l < L; ++l) {
+                if (l == g.gather_slot || !g.leaf_shadow[l]) continue;
+                double* p = g.leaf_shadow[l] + i;
+                if (g.leaf_acc[l])
+                    *p += a.get(l);
+                else
+                    *p = a.get(l);
+            }
+        }
+        if constexpr (AGG) {
+            if (scatter) {
+                if (ok) {
+                    const double ub = a.get(g.gather_slot);
+                    if constexpr (K > 0) {
+#pragma unroll
+                        for (int j = 0; j < K; ++j)
+                            agg_add(tab, row.c[j], row.b[j] * ub, g.gsrc_shadow, g.hash_shift);
+                    } else {
+                        for (int j = 0; j < g.gk; ++j)
+                            agg_add(tab, g.gconn[i * g.gk + j], g.gB[i * g.gk + j] * ub,
+                                    g.gsrc_shadow, g.hash_shift);
+                    }
+                }
+                __syncthreads();
+                agg_flush(tab, g.gsrc_shadow);
+            }
+        }
+    }
+}
+
+template <int K>
+hipError_t launch_group_k(const GroupDev& g, int mode, hipStream_t s) {
+    const dim3 grid((unsigned)group_blocks(g.n)), block(kGroupBlock);
+    switch (mode) {
+        case G_FWD: hipLaunchKernelGGL((k_group<K, G_FWD>), grid, block, 0, s, g); break;
+        case G_REV: hipLaunchKernelGGL((k_group<K, G_REV>), grid, block, 0, s, g); break;
+        default: hipLaunchKernelGGL((k_group<K, G_FWDREV>), grid, block, 0, s, g); break;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
+
+int64_t group_blocks(int64_t n) { return (n + kGroupBlock - 1) / kGroupBlock; }
+
+hipError_t launch_group(const GroupDev& g, int mode, hipStream_t s) {
+    if (g.n == 0) return hipSuccess;
+    if (g.gather_slot < 0) return launch_group_k<0>(g, mode, s);
+    const bool vec = (reinterpret_cast<uintptr_t>(g.gconn) % 16 == 0) &&
+                     (reinterpret_cast<uintptr_t>(g.gB) % 16 == 0);
+    if (vec) {
+        switch (g.gk) {
+            case 2: return launch_group_k<2>(g, mode, s);
+            case 3: return launch_group_k<3>(g, mode, s);
+            case 4: return launch_group_k<4>(g, mode, s);
+            case 8: return launch_group_k<8>(g, mode, s);
+            default: break;
+        }
+    }
+    return launch_group_k<-1>(g, mode, s);
+}
 
 hipError_t launch_prog_fwd(const ProgOpDev& o, hipStream_t s) {
     if (o.n == 0) return hipSuccess;
     switch (o.kind) {
-        case P_SCALE: hipLaunchKernelGGL(k_scale, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.a, o.alpha, o.y); break;
         case P_STENCIL: hipLaunchKernelGGL(k_stencil, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.a, o.taps, o.y); break;
         case P_GATHER: hipLaunchKernelGGL(k_gather, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.k, o.conn, o.B, o.a, o.y); break;
-        case P_ADD: hipLaunchKernelGGL(k_add, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.a, o.alpha, o.b, o.beta, o.y); break;
-        case P_MUL: hipLaunchKernelGGL(k_mul, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.a, o.b, o.y); break;
-        case P_MAP: hipLaunchKernelGGL(k_map, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.a, o.fn, o.y); break;
-        case P_SUM: hipLaunchKernelGGL(k_sum, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.a, o.y); break;
         case P_SCAN: return launch_scan(o.n, o.a, 0, o.scratch, o.y, 0, s);
         default: return hipErrorInvalidValue;
     }
@@ -269,20 +389,13 @@ hipError_t launch_prog_fwd(const ProgOpDev& o, hipStream_t s) {
 hipError_t launch_prog_rev(const ProgOpDev& o, hipStream_t s) {
     if (o.n == 0) return hipSuccess;
     switch (o.kind) {
-        case P_SCALE: hipLaunchKernelGGL(k_r_scale, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.yb, o.alpha, o.ab); break;
-        case P_STENCIL: hipLaunchKernelGGL(k_r_stencil, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.yb, o.taps, o.ab); break;
+        case P_STENCIL: hipLaunchKernelGGL(k_r_stencil, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.yb, o.taps, o.ab, o.accumulate); break;
         case P_GATHER: hipLaunchKernelGGL(k_r_gather, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.k, o.conn, o.B, o.yb, o.ab); break;
-        case P_ADD: hipLaunchKernelGGL(k_r_add, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.yb, o.alpha, o.ab, o.beta, o.bb); break;
-        case P_MUL: hipLaunchKernelGGL(k_r_mul, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.yb, o.a, o.b, o.ab, o.bb); break;
-        case P_MAP: hipLaunchKernelGGL(k_r_map, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.yb, o.a, o.fn, o.ab); break;
-        case P_SUM: hipLaunchKernelGGL(k_r_sum, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.alpha, o.ab); break;
-        case P_SCAN: return launch_scan(o.n, o.yb, 1, o.scratch, o.ab, 1, s);
+        case P_SCAN: return launch_scan(o.n, o.yb, 1, o.scratch, o.ab, o.accumulate, s);
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
-
-int64_t prog_sum_blocks(int64_t n) { return (n + kBS - 1) / kBS; }
 
 int64_t prog_scan_chunks(int64_t n) { return (n + kScanItems - 1) / kScanItems; }
 

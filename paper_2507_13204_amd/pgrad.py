@@ -37,8 +37,8 @@ EXPORTS = ("pg_default_options", "pg_mesh_plan", "pg_dense_plan", "pg_bdense_pla
            "pg_plan_destroy", "pg_last_error", "pg_version",
            "pg_prog_create", "pg_prog_input", "pg_prog_const", "pg_prog_scale", "pg_prog_stencil",
            "pg_prog_gather", "pg_prog_add", "pg_prog_mul", "pg_prog_map", "pg_prog_scan",
-           "pg_prog_sum", "pg_prog_plan", "pg_prog_bind_workspace", "pg_prog_run", "pg_prog_info",
-           "pg_prog_destroy")
+           "pg_prog_sum", "pg_prog_fusion", "pg_prog_plan", "pg_prog_bind_workspace", "pg_prog_run",
+           "pg_prog_info", "pg_prog_destroy")
 MAPS = {"square": 0, "psi": 1}
 
 
@@ -47,6 +47,14 @@ class PgError(RuntimeError):
         name = STATUS_NAMES[code] if 0 <= code < len(STATUS_NAMES) else str(code)
         super().__init__(f"{where}: {name}: {msg}")
         self.code = code
+
+
+class ProgStats(ctypes.Structure):
+    _fields_ = [("fwd_kernels", ctypes.c_int32), ("rev_kernels", ctypes.c_int32),
+                ("atomic_ops", ctypes.c_int32), ("rescheduled_ops", ctypes.c_int32),
+                ("groups", ctypes.c_int32), ("fused_gathers", ctypes.c_int32),
+                ("dead_ops", ctypes.c_int32), ("tape_bytes", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64)]
 
 
 class Options(ctypes.Structure):
@@ -114,7 +122,8 @@ def lib():
     L.pg_prog_plan.argtypes = [_VP, _SZP]
     L.pg_prog_bind_workspace.argtypes = [_VP, _VP, ctypes.c_size_t]
     L.pg_prog_run.argtypes = [_VP, ctypes.POINTER(_VP), _VP, ctypes.POINTER(_VP), _VP]
-    L.pg_prog_info.argtypes = [_VP, I32P, I32P, I32P, I32P, ctypes.POINTER(_I64)]
+    L.pg_prog_fusion.argtypes = [_VP, _I32]
+    L.pg_prog_info.argtypes = [_VP, ctypes.POINTER(ProgStats)]
     L.pg_prog_destroy.argtypes = [_VP]
     for name in EXPORTS:
         if name.startswith("pg_prog_"):
@@ -431,9 +440,10 @@ class Program:
     evaluates f and, when asked, the gradient with respect to every input.
     """
 
-    def __init__(self):
+    def __init__(self, fusion: int = 1):
         self._p = ctypes.c_void_p()
         check(lib().pg_prog_create(ctypes.byref(self._p)), "pg_prog_create")
+        check(lib().pg_prog_fusion(self._p, int(fusion)), "pg_prog_fusion")
         self._keep = []
         self._ws = None
         self.n_inputs = 0
@@ -441,13 +451,13 @@ class Program:
         self.workspace_bytes = 0
 
     @classmethod
-    def from_spec(cls, spec, device="cuda") -> "Program":
+    def from_spec(cls, spec, device="cuda", fusion: int = 1) -> "Program":
         """Build (not plan) a program from construct tuples: ("input", n),
         ("const", data), ("scale", a, alpha), ("stencil", a, offsets, coeffs),
         ("gather", a, conn, B), ("add", a, alpha, b, beta), ("mul", a, b),
         ("map", a, fn), ("scan", a), ("sum", a); array operands (NumPy or
         torch) are copied to the device."""
-        p = cls()
+        p = cls(fusion)
 
         def dev(a, dtype):
             t = a if isinstance(a, torch.Tensor) else torch.from_numpy(a)
@@ -547,12 +557,9 @@ class Program:
         return self
 
     def info(self) -> dict:
-        f, r, a, q = _I32(), _I32(), _I32(), _I32()
-        t = _I64()
-        check(lib().pg_prog_info(self._p, ctypes.byref(f), ctypes.byref(r), ctypes.byref(a),
-                                 ctypes.byref(q), ctypes.byref(t)), "pg_prog_info")
-        return {"fwd_kernels": f.value, "rev_kernels": r.value, "atomic_ops": a.value,
-                "rescheduled_ops": q.value, "tape_bytes": t.value}
+        st = ProgStats()
+        check(lib().pg_prog_info(self._p, ctypes.byref(st)), "pg_prog_info")
+        return {name: getattr(st, name) for name, _ in ProgStats._fields_}
 
     def run(self, inputs: Sequence[torch.Tensor], grads=True, stream=None, f_out=None):
         """f (0-d float64 tensor) and, when grads is True (or a list of output

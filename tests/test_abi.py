@@ -211,22 +211,67 @@ def test_program_plan_reports_the_generated_reverse_pass():
     sz = ctypes.c_size_t()
     assert L.pg_prog_plan(p, ctypes.byref(sz)) == P.OK
     assert sz.value > 0 and sz.value % P.WORKSPACE_ALIGN == 0
-    f, r, at, rs = (ctypes.c_int32() for _ in range(4))
-    tape = ctypes.c_int64()
-    assert L.pg_prog_info(p, ctypes.byref(f), ctypes.byref(r), ctypes.byref(at),
-                          ctypes.byref(rs), ctypes.byref(tape)) == P.OK
-    # forward: 7 one-launch constructs + the scan's 3 + the sum's 2
-    assert f.value == 7 + 3 + 2
-    # reverse: s1, a, g, m, q (one launch each), the scan (3), the seed broadcast
-    assert r.value == 5 + 3 + 1
-    assert at.value == 1 and rs.value == 1
-    assert tape.value == 8 * (3 * n + 5 * E)  # every intermediate view is recorded
-    # workspace holds at least the tape and the active shadows
-    assert sz.value >= tape.value + 8 * (2 * n + 4 * E)
+    st = P.ProgStats()
+    assert L.pg_prog_info(p, ctypes.byref(st)) == P.OK
+    # Groups: {a} (sealed when the gather g reads it), {m} (sealed by the scan),
+    # {q + sum}.  The gather g is read only by group {m} and runs inside it;
+    # gc, read by the same group, stays a kernel of its own.
+    assert st.groups == 3 and st.fused_gathers == 1 and st.dead_ops == 0
+    # forward: s1, s2, gc, the scan's 3, three groups, the final reduction
+    assert st.fwd_kernels == 3 + 3 + 3 + 1
+    # reverse: s1, the scan's 3, groups {a} and {m}; inactive s2 and gc have
+    # none; the sum group runs its reverse inside its forward launch
+    assert st.rev_kernels == 1 + 3 + 2
+    assert st.atomic_ops == 1 and st.rescheduled_ops == 1
+    # recorded: s1, s2, gc, the scan (stand-alone outputs), a and m (exports)
+    assert st.tape_bytes == 8 * (3 * n + 3 * E)
+    assert sz.value == st.workspace_bytes
+    # plus shadows of s1, a, m, the scan and the input
+    assert sz.value >= st.tape_bytes + 8 * (3 * n + 2 * E)
     # binding checks size and alignment before any device work
     assert L.pg_prog_bind_workspace(p, None, sz.value) == P.EWORKSPACE
     assert L.pg_prog_bind_workspace(p, FAKE + 8, sz.value) == P.EWORKSPACE
     assert L.pg_prog_bind_workspace(p, FAKE, sz.value - 1) == P.EWORKSPACE
     ins = (ctypes.c_void_p * 1)(FAKE)
     assert L.pg_prog_run(p, ins, None, None, None) == P.ESTATE       # no workspace bound
+    L.pg_prog_destroy(p)
+
+
+def _mesh_program(L, p, n=500, E=400, k=8):
+    _, x = _v(L.pg_prog_input, p, n)
+    _, u = _v(L.pg_prog_gather, p, x, E, k, FAKE, FAKE)
+    _, s = _v(L.pg_prog_map, p, u, 1)
+    _, w = _v(L.pg_prog_const, p, E, FAKE)
+    _, t = _v(L.pg_prog_mul, p, s, w)
+    _, dead = _v(L.pg_prog_scale, p, t, 2.0)          # feeds nothing
+    assert L.pg_prog_sum(p, t) == P.OK
+
+
+@pytest.mark.parametrize("fusion", [0, 1])
+def test_mesh_program_plan(fusion):
+    L, p = _prog()
+    assert L.pg_prog_fusion(p, fusion) == P.OK
+    _mesh_program(L, p)
+    sz = ctypes.c_size_t()
+    assert L.pg_prog_plan(p, ctypes.byref(sz)) == P.OK
+    st = P.ProgStats()
+    assert L.pg_prog_info(p, ctypes.byref(st)) == P.OK
+    assert st.dead_ops == 1 and st.atomic_ops == 1
+    if fusion:
+        # gather -> map -> mul -> sum is one kernel computing f and the gradient
+        assert (st.groups, st.fused_gathers, st.fwd_kernels, st.rev_kernels) == (1, 1, 2, 0)
+        assert st.tape_bytes == 0
+    else:
+        # one kernel per construct (the sum's partials taken by the mul kernel),
+        # then the final reduction; reverse: mul (seeded), map, the gather's
+        # atomic scatter; recorded: the gather's and the map's outputs
+        assert (st.groups, st.fused_gathers, st.fwd_kernels, st.rev_kernels) == (2, 0, 4, 3)
+        assert st.tape_bytes == 8 * 2 * 400
+    L.pg_prog_destroy(p)
+
+
+def test_program_fusion_level_is_checked():
+    L, p = _prog()
+    assert L.pg_prog_fusion(p, 2) == P.EINVAL
+    assert L.pg_prog_info(p, ctypes.byref(P.ProgStats())) == P.ESTATE
     L.pg_prog_destroy(p)

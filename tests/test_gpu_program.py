@@ -13,16 +13,19 @@ from _helpers import TOL_F64_F, TOL_F64_G, rel, srel, to_dev
 pytestmark = pytest.mark.gpu
 
 
-def run_case(case, grads=True):
-    prog = P.Program.from_spec(case.spec).plan()
+FUSION = [0, 1]
+
+
+def run_case(case, grads=True, fusion=1):
+    prog = P.Program.from_spec(case.spec, fusion=fusion).plan()
     xs = [to_dev(x) for x in case.inputs]
     out = prog.run(xs, grads=grads)
     torch.cuda.synchronize()
     return prog, out
 
 
-def check_case(case):
-    prog, (f, gs) = run_case(case)
+def check_case(case, fusion=1):
+    prog, (f, gs) = run_case(case, fusion=fusion)
     f_ref, g_ref = OP.gradient(case.spec, case.inputs)
     assert srel(f.item(), f_ref) < TOL_F64_F, (case.name, f.item(), f_ref)
     for g, gr in zip(gs, g_ref):
@@ -30,36 +33,41 @@ def check_case(case):
     return prog
 
 
+@pytest.mark.parametrize("fusion", FUSION)
 @pytest.mark.parametrize("n,E,k,hot", [(1000, 777, 4, 0), (300, 3000, 8, 4), (2500, 513, 3, 0),
-                                       (257, 64, 1, 0)])
-def test_mix_program(n, E, k, hot):
-    prog = check_case(inputs.program_mix(n, E, k, seed=7, hot=hot))
+                                       (257, 64, 1, 0), (700, 900, 5, 0), (64, 5000, 2, 0)])
+def test_mix_program(n, E, k, hot, fusion):
+    prog = check_case(inputs.program_mix(n, E, k, seed=7, hot=hot), fusion)
     info = prog.info()
     assert info["atomic_ops"] == 1 and info["rescheduled_ops"] == 1
+    assert info["fused_gathers"] == fusion
 
 
+@pytest.mark.parametrize("fusion", FUSION)
 @pytest.mark.parametrize("n", [1, 2, 3, 255, 1000, 10_000])
-def test_paper_program(n, orc):
+def test_paper_program(n, fusion, orc):
     case = inputs.program_paper(n, seed=9)
-    check_case(case)
+    check_case(case, fusion)
     # and the same numbers as the hand-fused section 4 path
-    _, (f, (gx, gb)) = run_case(case)
+    _, (f, (gx, gb)) = run_case(case, fusion=fusion)
     f2, gx2, gb2 = orc.laplace1d_gradient(*case.inputs)
     assert srel(f.item(), f2) < TOL_F64_F
     assert rel(gx.cpu().numpy(), gx2) < TOL_F64_G and rel(gb.cpu().numpy(), gb2) < TOL_F64_G
 
 
+@pytest.mark.parametrize("fusion", FUSION)
 @pytest.mark.parametrize("s", [2, 9, 17])
-def test_mesh_program(s, orc):
+def test_mesh_program(s, fusion, orc):
     m = inputs.hex_mesh(s, seed=31)
     case = inputs.program_mesh(m)
-    check_case(case)
-    _, (f, (g,)) = run_case(case)
+    check_case(case, fusion)
+    _, (f, (g,)) = run_case(case, fusion=fusion)
     f2, g2 = orc.mesh_gradient(m.n_nodes, m.conn, m.B, m.w, m.x)
     assert srel(f.item(), f2) < TOL_F64_F and rel(g.cpu().numpy(), g2) < TOL_F64_G
 
 
-def test_scan_across_many_chunks():
+@pytest.mark.parametrize("fusion", FUSION)
+def test_scan_across_many_chunks(fusion):
     n = 200_003  # 98 scan chunks of 2048 and a ragged tail
     rng = np.random.default_rng(17)
     x = rng.uniform(-1, 1, n)
@@ -67,7 +75,7 @@ def test_scan_across_many_chunks():
     spec = [("input", n), ("scan", 0), ("map", 1, "psi"), ("const", w), ("mul", 2, 3),
             ("sum", 4)]
     case = inputs.ProgramCase(spec, [x], "scan")
-    _, (f, (g,)) = run_case(case)
+    _, (f, (g,)) = run_case(case, fusion=fusion)
     vals = OP.values(spec, [x])
     assert srel(f.item(), vals[-1]) < TOL_F64_F
     idx = [0, 1, 2047, 2048, 4095, 100_000, n - 2, n - 1]
@@ -118,3 +126,65 @@ def test_gather_connectivity_is_checked_at_bind():
     with pytest.raises(P.PgError) as e:
         P.Program.from_spec(spec).plan()
     assert e.value.code == P.ERANGE
+
+
+def _rand(n, seed):
+    return np.random.default_rng(seed).uniform(-1, 1, n)
+
+
+@pytest.mark.parametrize("fusion", FUSION)
+def test_sum_of_an_input_and_of_a_gather(fusion):
+    n = 1025
+    x = _rand(n, 1)
+    check_case(inputs.ProgramCase([("input", n), ("sum", 0)], [x], "sum-input"), fusion)
+    rng = np.random.default_rng(2)
+    conn = rng.integers(0, n, size=(3000, 4)).astype(np.int32)
+    B = rng.standard_normal((3000, 4))
+    check_case(inputs.ProgramCase([("input", n), ("gather", 0, conn, B), ("sum", 1)], [x],
+                                  "sum-gather"), fusion)
+
+
+@pytest.mark.parametrize("fusion", FUSION)
+def test_gather_whose_operand_the_group_also_reads(fusion):
+    # E == n: the group reads x both through the gather and directly, so the
+    # gather must not be fused (a store and atomics into one shadow).
+    n = 2000
+    rng = np.random.default_rng(3)
+    x = _rand(n, 4)
+    conn = rng.integers(0, n, size=(n, 8)).astype(np.int32)
+    B = rng.standard_normal((n, 8)) / 3
+    spec = [("input", n), ("gather", 0, conn, B), ("mul", 1, 0), ("map", 2, "psi"), ("sum", 3)]
+    prog = check_case(inputs.ProgramCase(spec, [x], "gather-and-leaf"), fusion)
+    assert prog.info()["fused_gathers"] == 0
+
+
+@pytest.mark.parametrize("fusion", FUSION)
+def test_long_chain_and_many_leaves(fusion):
+    # 20 pointwise constructs over 10 inputs: more than one group's slots,
+    # leaves and ops, so the planner has to split.
+    n = 3001
+    xs = [_rand(n, 10 + i) for i in range(10)]
+    spec = [("input", n) for _ in range(10)]
+    cur = 0
+    for i in range(1, 10):
+        spec.append(("add", cur, 0.9, i, 0.3))
+        cur = len(spec) - 1
+        spec.append(("map", cur, "psi" if i % 2 else "square"))
+        cur = len(spec) - 1
+        spec.append(("scale", cur, 0.5))
+        cur = len(spec) - 1
+    spec.append(("mul", cur, cur))
+    spec.append(("sum", len(spec) - 1))
+    prog = check_case(inputs.ProgramCase(spec, xs, "long-chain"), fusion)
+    if fusion:
+        assert prog.info()["groups"] > 1
+
+
+@pytest.mark.parametrize("fusion", FUSION)
+def test_self_add_and_shared_leaf(fusion):
+    n = 777
+    x, y = _rand(n, 5), _rand(n, 6)
+    spec = [("input", n), ("input", n), ("add", 0, 1.5, 0, -0.25), ("mul", 2, 1),
+            ("stencil", 3, [0, -1], [1.0, 0.5]), ("add", 4, 1.0, 3, 1.0), ("mul", 5, 0),
+            ("sum", 6)]
+    check_case(inputs.ProgramCase(spec, [x, y], "self-add"), fusion)
