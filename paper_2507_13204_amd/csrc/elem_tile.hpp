@@ -127,6 +127,7 @@ __device__ __forceinline__ void agg_clear(AggTable& t) {
 __device__ __forceinline__ void agg_add(AggTable& t, int32_t n, double c, double* g,
                                         uint32_t shift) {
     uint32_t h = agg_hash(n, shift);
+#pragma nounroll
     for (int probe = 0; probe < kMaxProbe; ++probe) {
         const int32_t old = atomicCAS(&t.key[h], -1, n);
         if (old == -1 || old == n) {

@@ -272,8 +272,11 @@ struct GroupDev {
 
 enum GroupMode { G_FWD = 0, G_REV = 1, G_FWDREV = 2 };
 
+// Workgroup size of a group launch (the number of sum partials it writes is
+// group_blocks(n, group_block_size(g, mode))).
+constexpr int kGroupBlock = 256, kGroupBlockScatter = 512;
 hipError_t launch_group(const GroupDev& g, int mode, hipStream_t s);
-int64_t group_blocks(int64_t n);
-constexpr int kGroupBlock = 256;
+int64_t group_blocks(int64_t n, int bs);
+int group_block_size(const GroupDev& g, int mode);
 
 }  // namespace pg

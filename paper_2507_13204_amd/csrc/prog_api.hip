@@ -513,7 +513,8 @@ pg_status pg_prog_plan(pg_prog p, size_t* workspace_bytes) {
     for (const Op& op : ops)
         if (op.kind == P_INPUT)
             p->input_shadow_off[(size_t)op.input_index] = take(sizeof(double) * (size_t)op.n);
-    p->partials_off = take(sizeof(double) * (size_t)std::max<int64_t>(group_blocks(ops[(size_t)S].n), 1));
+    p->partials_off =
+        take(sizeof(double) * (size_t)std::max<int64_t>(group_blocks(ops[(size_t)S].n, kGroupBlock), 1));
     p->fscratch_off = take(sizeof(double));
     p->flag_off = take(sizeof(int32_t) * 4);
     int64_t scan_chunks = 0;  // one totals buffer, reused by every scan in turn
@@ -578,7 +579,7 @@ pg_status pg_prog_bind_workspace(pg_prog p, void* ws, size_t bytes) {
     for (Group& g : p->groups) {
         if (g.gather < 0) continue;
         const Op& op = p->ops[(size_t)g.gather];
-        const int64_t span = kGroupBlock, nt = (op.n + span - 1) / span;
+        const int64_t span = kGroupBlockScatter, nt = (op.n + span - 1) / span;
         const int64_t ns = std::min<int64_t>(nt, 24);
         std::vector<std::vector<int32_t>> tiles;
         for (int64_t q = 0; q < ns; ++q) {
@@ -660,7 +661,7 @@ pg_status pg_prog_run(pg_prog p, const double* const* inputs, double* f_out, dou
             o.b = op.b >= 0 ? slot(op.b) : 0;
             o.fn = op.fn;
             o.alpha = op.alpha;
-            o.beta = op.beta;
+            o.beta = op.kind == P_ADD ? op.beta : 0.0;  // the kernel reads scale as alpha a + 0 b
             if (op.exported) {
                 d.export_slot[d.n_exports] = (int32_t)(g.leaves.size() + m);
                 d.export_val[d.n_exports] = at(p, op.val_off);
@@ -708,15 +709,18 @@ pg_status pg_prog_run(pg_prog p, const double* const* inputs, double* f_out, dou
             PG_HIP(launch_zero(shd[(size_t)v], sizeof(double) * (size_t)ops[(size_t)v].n, s));
     // Forward pass; with fusion the sum group runs its reverse in the same pass.
     const bool fused_last = rev && p->fusion;
+    int64_t n_partials = 0;
     for (const Item& it : p->sched) {
         if (it.group) {
             const int mode = (it.id == p->sum_group && fused_last) ? G_FWDREV : G_FWD;
-            PG_HIP(launch_group(group_dev(it.id), mode, s));
+            const GroupDev d = group_dev(it.id);
+            if (it.id == p->sum_group) n_partials = group_blocks(n_sum, group_block_size(d, mode));
+            PG_HIP(launch_group(d, mode, s));
         } else {
             PG_HIP(launch_prog_fwd(op_dev(it.id), s));
         }
     }
-    PG_HIP(launch_final_sum(partials, group_blocks(n_sum), f_out ? f_out : at(p, p->fscratch_off), s));
+    PG_HIP(launch_final_sum(partials, n_partials, f_out ? f_out : at(p, p->fscratch_off), s));
     if (!rev) return PG_OK;
     // Reverse pass: the schedule backwards, reads turned into deliveries.
     for (size_t r = p->sched.size(); r-- > 0;) {

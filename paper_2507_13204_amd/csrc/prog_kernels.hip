@@ -178,39 +178,51 @@ hipError_t launch_scan(int64_t n, const double* a, int rev, double* scratch, dou
 
 // ------------------------------------------------------------ fused groups
 
-// Sixteen FP64 slots addressed by a wave-uniform index.  A private array
-// indexed at run time would live in scratch memory; named members selected
-// by a switch on a uniform index stay in VGPRs and cost scalar branches only.
-#define PG_SLOTS(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
+// NS FP64 slots addressed by a wave-uniform index.  A private array indexed
+// at run time would live in scratch memory; here every access is a switch on
+// the uniform index whose cases use constant indices, so the slots stay in
+// VGPRs and an access costs a few scalar branches.  (Chains of selects over
+// the slots measured twice as slow on the 128^3 mesh program.)  Launches
+// pick the smallest NS (4, 8 or 16) that holds the group's leaves and ops.
+#define PG_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
+template <int NS>
 struct Slots {
-#define PG_DECL(i) double r##i = 0.0;
-    PG_SLOTS(PG_DECL)
-#undef PG_DECL
+    double r[NS];
+    __device__ __forceinline__ Slots() {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) r[q] = 0.0;
+    }
     __device__ __forceinline__ double get(int i) const {
         switch (i) {
-#define PG_GET(i) case i: return r##i;
-            PG_SLOTS(PG_GET)
+#define PG_GET(q) \
+    case q:       \
+        if constexpr (q < NS) return r[q < NS ? q : 0]; else return 0.0;
+            PG_CASES(PG_GET)
 #undef PG_GET
         }
         return 0.0;
     }
     __device__ __forceinline__ void set(int i, double v) {
         switch (i) {
-#define PG_SET(i) case i: r##i = v; break;
-            PG_SLOTS(PG_SET)
+#define PG_SET(q) \
+    case q:       \
+        if constexpr (q < NS) r[q < NS ? q : 0] = v; break;
+            PG_CASES(PG_SET)
 #undef PG_SET
         }
     }
     __device__ __forceinline__ void add(int i, double v) {
         switch (i) {
-#define PG_ADD(i) case i: r##i += v; break;
-            PG_SLOTS(PG_ADD)
+#define PG_ADD(q) \
+    case q:       \
+        if constexpr (q < NS) r[q < NS ? q : 0] += v; break;
+            PG_CASES(PG_ADD)
 #undef PG_ADD
         }
     }
 };
-#undef PG_SLOTS
-static_assert(kGSlots == 16, "Slots holds sixteen values");
+#undef PG_CASES
+static_assert(kGSlots == 16, "at most sixteen slots");
 
 // Row of the fused gather: K > 0 keeps it in registers (vector loads);
 // K < 0 is the generic row length, read again in the reverse scatter.
@@ -221,51 +233,42 @@ struct GatherRow {
     double b[N];
 };
 
-template <int K>
-__device__ __forceinline__ double gather_value(const GroupDev& g, int64_t i, GatherRow<K>& row) {
-    double u = 0.0;
-    if constexpr (K > 0) {
-        load_conn_row<double, K>(g.gconn, i, row.c);
-        load_b_row<K>(g.gB, i, row.b);
-        double xv[K];
-#pragma unroll
-        for (int j = 0; j < K; ++j) xv[j] = g.gsrc[row.c[j]];
-#pragma unroll
-        for (int j = 0; j < K; ++j) u += row.b[j] * xv[j];
-    } else {
-        for (int j = 0; j < g.gk; ++j) u += g.gB[i * g.gk + j] * g.gsrc[g.gconn[i * g.gk + j]];
-    }
-    return u;
-}
-
-template <int K, int MODE>
-__global__ void __launch_bounds__(kGroupBlock) k_group(GroupDev g) {
+// K: fused gather row length (0 none, -1 generic); NS: slots; BS: workgroup.
+template <int K, int MODE, int BS, int NS>
+__global__ void __launch_bounds__(BS) k_group(GroupDev g) {
     constexpr bool REV = MODE != G_FWD;
     constexpr bool FWD = MODE != G_REV;
     constexpr bool AGG = REV && K != 0;
-    __shared__ double lds[kGroupBlock / kWave];
+    constexpr int NL = NS < kGLeaves ? NS : kGLeaves;
+    __shared__ double lds[BS / kWave];
     __shared__ typename std::conditional<AGG, AggTable, int>::type tab;
     const bool scatter = AGG && g.gsrc_shadow != nullptr;
-    if constexpr (AGG) {
-        if (scatter) {
-            agg_clear(tab);
-            __syncthreads();
-        }
-    }
-    const int64_t i = xcd_remap(blockIdx.x, gridDim.x) * kGroupBlock + threadIdx.x;
+    const int64_t i = xcd_remap(blockIdx.x, gridDim.x) * BS + threadIdx.x;
     const bool ok = i < g.n;
     const int L = g.n_leaves;
-    Slots r;
+    Slots<NS> r;
     GatherRow<K> row;
     if (ok) {
-        for (int l = 0; l < L; ++l) {
-            if constexpr (K != 0) {
-                if (l == g.gather_slot) {
-                    r.set(l, gather_value<K>(g, i, row));
-                    continue;
-                }
-            }
-            r.set(l, g.leaf[l][i]);
+        // Every load first: the gather row, the leaves, then the gathered entries.
+        if constexpr (K > 0) {
+            load_conn_row<double, K>(g.gconn, i, row.c);
+            load_b_row<K>(g.gB, i, row.b);
+        }
+#pragma unroll
+        for (int l = 0; l < NL; ++l)
+            if (l < L && l != g.gather_slot) r.r[l] = g.leaf[l][i];
+        if constexpr (K > 0) {
+            double xv[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) xv[j] = g.gsrc[row.c[j]];
+            double u = 0.0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) u += row.b[j] * xv[j];
+            r.set(g.gather_slot, u);
+        } else if constexpr (K < 0) {
+            double u = 0.0;
+            for (int j = 0; j < g.gk; ++j) u += g.gB[i * g.gk + j] * g.gsrc[g.gconn[i * g.gk + j]];
+            r.set(g.gather_slot, u);
         }
         for (int j = 0; j < g.n_ops; ++j) {
             const GOp o = g.ops[j];
@@ -285,12 +288,12 @@ __global__ void __launch_bounds__(kGroupBlock) k_group(GroupDev g) {
     }
     if constexpr (FWD) {
         if (g.sum_slot >= 0) {
-            const double t = block_sum<kGroupBlock>(ok ? r.get(g.sum_slot) : 0.0, lds);
+            const double t = block_sum<BS>(ok ? r.get(g.sum_slot) : 0.0, lds);
             if (threadIdx.x == 0) g.partials[blockIdx.x] = t;
         }
     }
     if constexpr (REV) {
-        Slots a;
+        Slots<NS> a;
         if (ok) {
             if (g.sum_slot >= 0) a.add(g.sum_slot, g.seed);
             for (int x = 0; x < g.n_exports; ++x)
@@ -313,17 +316,21 @@ __global__ void __launch_bounds__(kGroupBlock) k_group(GroupDev g) {
                     default: a.add(o.a, map_df(o.fn, r.get(o.a)) * yb); break;
                 }
             }
-            for (int l = 0; l < L; ++l) {
-                if (l == g.gather_slot || !g.leaf_shadow[l]) continue;
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                if (l >= L || l == g.gather_slot || !g.leaf_shadow[l]) continue;
                 double* p = g.leaf_shadow[l] + i;
                 if (g.leaf_acc[l])
-                    *p += a.get(l);
+                    *p += a.r[l];
                 else
-                    *p = a.get(l);
+                    *p = a.r[l];
             }
         }
         if constexpr (AGG) {
             if (scatter) {
+                // The table is cleared only now, so the loads above were not held up.
+                agg_clear(tab);
+                __syncthreads();
                 if (ok) {
                     const double ub = a.get(g.gather_slot);
                     if constexpr (K > 0) {
@@ -343,36 +350,55 @@ __global__ void __launch_bounds__(kGroupBlock) k_group(GroupDev g) {
     }
 }
 
-template <int K>
+template <int K, int NS>
 hipError_t launch_group_k(const GroupDev& g, int mode, hipStream_t s) {
-    const dim3 grid((unsigned)group_blocks(g.n)), block(kGroupBlock);
+    constexpr int BS = kGroupBlock, BSS = K != 0 ? kGroupBlockScatter : kGroupBlock;
+    const dim3 grid((unsigned)group_blocks(g.n, BS)), block(BS);
+    const dim3 grid_s((unsigned)group_blocks(g.n, BSS)), block_s(BSS);
     switch (mode) {
-        case G_FWD: hipLaunchKernelGGL((k_group<K, G_FWD>), grid, block, 0, s, g); break;
-        case G_REV: hipLaunchKernelGGL((k_group<K, G_REV>), grid, block, 0, s, g); break;
-        default: hipLaunchKernelGGL((k_group<K, G_FWDREV>), grid, block, 0, s, g); break;
+        case G_FWD: hipLaunchKernelGGL((k_group<K, G_FWD, BS, NS>), grid, block, 0, s, g); break;
+        case G_REV: hipLaunchKernelGGL((k_group<K, G_REV, BSS, NS>), grid_s, block_s, 0, s, g); break;
+        default: hipLaunchKernelGGL((k_group<K, G_FWDREV, BSS, NS>), grid_s, block_s, 0, s, g); break;
     }
     return hipGetLastError();
 }
 
+template <int K>
+hipError_t launch_group_ns(const GroupDev& g, int mode, hipStream_t s) {
+    const int need = g.n_leaves + g.n_ops;
+    if (need <= 4) return launch_group_k<K, 4>(g, mode, s);
+    if (need <= 8) return launch_group_k<K, 8>(g, mode, s);
+    return launch_group_k<K, 16>(g, mode, s);
+}
+
 }  // namespace
 
-int64_t group_blocks(int64_t n) { return (n + kGroupBlock - 1) / kGroupBlock; }
+int64_t group_blocks(int64_t n, int bs) { return (n + bs - 1) / bs; }
+
+// A group with a fused gather scatters through the LDS table in its reverse
+// pass; a larger workgroup combines more contributions per table clear and
+// flush (512 threads measured best for eight-node rows, as for the mesh).
+int group_block_size(const GroupDev& g, int mode) {
+    return (g.gather_slot >= 0 && mode != G_FWD) ? kGroupBlockScatter : kGroupBlock;
+}
 
 hipError_t launch_group(const GroupDev& g, int mode, hipStream_t s) {
     if (g.n == 0) return hipSuccess;
-    if (g.gather_slot < 0) return launch_group_k<0>(g, mode, s);
+    if (g.n_leaves + g.n_ops > kGSlots || g.n_leaves > kGLeaves || g.n_ops > kGOps)
+        return hipErrorInvalidValue;
+    if (g.gather_slot < 0) return launch_group_ns<0>(g, mode, s);
     const bool vec = (reinterpret_cast<uintptr_t>(g.gconn) % 16 == 0) &&
                      (reinterpret_cast<uintptr_t>(g.gB) % 16 == 0);
     if (vec) {
         switch (g.gk) {
-            case 2: return launch_group_k<2>(g, mode, s);
-            case 3: return launch_group_k<3>(g, mode, s);
-            case 4: return launch_group_k<4>(g, mode, s);
-            case 8: return launch_group_k<8>(g, mode, s);
+            case 2: return launch_group_ns<2>(g, mode, s);
+            case 3: return launch_group_ns<3>(g, mode, s);
+            case 4: return launch_group_ns<4>(g, mode, s);
+            case 8: return launch_group_ns<8>(g, mode, s);
             default: break;
         }
     }
-    return launch_group_k<-1>(g, mode, s);
+    return launch_group_ns<-1>(g, mode, s);
 }
 
 hipError_t launch_prog_fwd(const ProgOpDev& o, hipStream_t s) {
