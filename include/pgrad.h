@@ -261,6 +261,19 @@ pg_status pg_prog_map(pg_prog prog, int32_t a, pg_map_fn fn, int32_t* view);
  * sum_{i >= j} ybar_i: the rule the paper's conclusion lists as missing for
  * parallel_scan.  Fixed summation order (deterministic). */
 pg_status pg_prog_scan(pg_prog prog, int32_t a, int32_t* view);
+/* y_s = sum of a over [offsets[s], offsets[s+1]) for s < n_seg (a partial
+ * parallel_reduce); its reverse broadcasts the output shadow over each
+ * segment (section 3.2: a reduction's adjoint is a broadcast).  offsets:
+ * device int64, n_seg + 1 entries, kept, not owned; checked in
+ * pg_prog_bind_workspace (PG_ERANGE unless 0 = offsets[0] <= ... <=
+ * offsets[n_seg] = length of a).  One wave per segment, fixed order. */
+pg_status pg_prog_segment_sum(pg_prog prog, int32_t a, int64_t n_seg, const int64_t* offsets,
+                              int32_t* view);
+/* y_i = a_s for offsets[s] <= i < offsets[s+1] (n_out = offsets[len(a)]
+ * outputs); the reverse is the segment sum of the output shadow.  offsets:
+ * as above with n_seg = length of a, last entry n_out. */
+pg_status pg_prog_broadcast(pg_prog prog, int32_t a, const int64_t* offsets, int64_t n_out,
+                            int32_t* view);
 /* f = sum of view a.  Ends the program. */
 pg_status pg_prog_sum(pg_prog prog, int32_t a);
 /* Checks the program, runs the activity analysis, lays out the tape and the

@@ -17,6 +17,8 @@ parallel sum).  Constructs, as tuples:
     ("map", a, fn)                      y = fn(a): "square" (s^2) or "psi" (the element
                                         nonlinearity psi(s) = s^2/2 + log(1 + s^2)/2)
     ("scan", a)                         y_i = sum_{j <= i} a_j (inclusive prefix sum)
+    ("segsum", a, offsets)              y_s = sum of a over [offsets[s], offsets[s+1])
+    ("bcast", a, offsets)               y_i = a_s for offsets[s] <= i < offsets[s+1]
     ("sum", a)                          f = sum of view a; must come last
 
 View ids are the positions of the constructs in the list.
@@ -83,6 +85,14 @@ def _scan_matrix(n: int) -> sp.csr_matrix:
     return sp.csr_matrix(np.tril(np.ones((n, n))))
 
 
+def _segment_matrix(offsets) -> sp.csr_matrix:
+    """S[s, i] = 1 for offsets[s] <= i < offsets[s+1]: the segment sum."""
+    off = np.asarray(offsets, dtype=np.int64)
+    n_seg, n = len(off) - 1, int(off[-1])
+    rows = np.repeat(np.arange(n_seg), np.diff(off))
+    return sp.csr_matrix((np.ones(n), (rows, np.arange(n))), shape=(n_seg, n))
+
+
 def lengths(spec) -> List[int]:
     """Length of every view (the sum construct gets length 1)."""
     out: List[int] = []
@@ -94,6 +104,10 @@ def lengths(spec) -> List[int]:
             out.append(len(op[1]))
         elif k == "gather":
             out.append(len(op[2]))
+        elif k == "segsum":
+            out.append(len(op[2]) - 1)
+        elif k == "bcast":
+            out.append(int(op[2][-1]))
         elif k == "sum":
             out.append(1)
         else:
@@ -127,6 +141,10 @@ def values(spec, inputs: Sequence[np.ndarray]) -> list:
             vals.append(_phi(op[2], vals[op[1]]))
         elif k == "scan":
             vals.append(np.cumsum(vals[op[1]]))
+        elif k == "segsum":
+            vals.append(_segment_matrix(op[2]) @ vals[op[1]])
+        elif k == "bcast":
+            vals.append(_segment_matrix(op[2]).T @ vals[op[1]])
         elif k == "sum":
             v = vals[op[1]]
             vals.append(math.fsum(v) if np.isrealobj(v) else np.sum(v))
@@ -177,6 +195,10 @@ def gradient(spec, inputs: Sequence[np.ndarray]) -> Tuple[float, List[np.ndarray
             acc(op[1], sp.diags(_dphi(op[2], vals[op[1]]), format="csr"))
         elif k == "scan":
             acc(op[1], _scan_matrix(len(vals[v])))
+        elif k == "segsum":
+            acc(op[1], _segment_matrix(op[2]))
+        elif k == "bcast":
+            acc(op[1], _segment_matrix(op[2]).T.tocsr())
         elif k == "sum":
             acc(op[1], sp.csr_matrix(np.ones((1, len(vals[op[1]])))))
         jac.append(J)

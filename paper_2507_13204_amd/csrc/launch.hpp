@@ -197,7 +197,8 @@ namespace pg {
 
 // ------------------------------------------------------- composed programs
 
-enum ProgKind { P_INPUT = 0, P_CONST = 1, P_SCALE, P_STENCIL, P_GATHER, P_ADD, P_MUL, P_MAP, P_SUM, P_SCAN };
+enum ProgKind { P_INPUT = 0, P_CONST = 1, P_SCALE, P_STENCIL, P_GATHER, P_ADD, P_MUL, P_MAP, P_SUM, P_SCAN,
+                P_SEGSUM, P_BCAST };
 
 constexpr int kMaxTaps = 16;
 
@@ -207,11 +208,14 @@ struct ProgTaps {
     double coef[kMaxTaps] = {};
 };
 
-// One non-pointwise construct (stencil, gather, scan) as its kernels see it.
-// Forward: y = op(a).  Reverse: ab receives the adjoint of the output shadow
-// yb, stored (accumulate 0) or added (accumulate 1); the gather's reverse is
-// always an atomic addition.  The scan uses scratch (prog_scan_chunks(n)
-// doubles) for its chunk totals.
+// One non-pointwise construct (stencil, gather, scan, segment sum,
+// broadcast) as its kernels see it.  Forward: y = op(a) over n outputs.
+// Reverse: ab receives the adjoint of the output shadow yb, stored
+// (accumulate 0) or added (accumulate 1); the gather's reverse is always an
+// atomic addition.  The scan uses scratch (prog_scan_chunks(n) doubles) for
+// its chunk totals.  Segment sum and broadcast take segment offsets offs
+// (n_seg + 1 entries): the sum has n = n_seg outputs, the broadcast n =
+// offs[n_seg].
 struct ProgOpDev {
     int kind = 0;
     int64_t n = 0;
@@ -225,11 +229,17 @@ struct ProgOpDev {
     double* ab = nullptr;
     int accumulate = 1;
     double* scratch = nullptr;
+    const int64_t* offs = nullptr;
+    int64_t n_seg = 0;
 };
 
 hipError_t launch_prog_fwd(const ProgOpDev& o, hipStream_t s);
 hipError_t launch_prog_rev(const ProgOpDev& o, hipStream_t s);
 int64_t prog_scan_chunks(int64_t n);
+// Sets *flag nonzero unless offs[0] == 0, offs is non-decreasing and
+// offs[n_seg] == n.
+hipError_t launch_validate_offsets(const int64_t* offs, int64_t n_seg, int64_t n, int32_t* flag,
+                                   hipStream_t s);
 
 // A fused group: a chain of pointwise constructs (scale, add, mul, map) over
 // one index range, evaluated per entry in registers.  Slots 0..n_leaves-1

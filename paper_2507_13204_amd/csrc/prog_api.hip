@@ -50,6 +50,8 @@ struct Op {
     const int32_t* conn = nullptr;
     const double* B = nullptr;
     const double* data = nullptr;  // P_CONST
+    const int64_t* offs = nullptr; // P_SEGSUM, P_BCAST: segment offsets (n_seg + 1)
+    int64_t n_seg = 0;
     int32_t input_index = -1;      // P_INPUT
     // plan
     bool live = false;       // feeds the summed view
@@ -266,6 +268,40 @@ pg_status pg_prog_scan(pg_prog p, int32_t a, int32_t* view) {
     return add_view(p, op, view);
 }
 
+pg_status pg_prog_segment_sum(pg_prog p, int32_t a, int64_t n_seg, const int64_t* offsets,
+                              int32_t* view) {
+    clear_error();
+    if (!p) return perr(PG_EINVAL, "program is NULL");
+    pg_status st = check_view(p, a);
+    if (st) return st;
+    if (n_seg < 0 || n_seg >= (1LL << 31) || !offsets)
+        return perr(PG_EINVAL, "n_seg out of range or offsets NULL");
+    Op op;
+    op.kind = P_SEGSUM;
+    op.n = n_seg;
+    op.a = a;
+    op.offs = offsets;
+    op.n_seg = n_seg;
+    return add_view(p, op, view);
+}
+
+pg_status pg_prog_broadcast(pg_prog p, int32_t a, const int64_t* offsets, int64_t n_out,
+                            int32_t* view) {
+    clear_error();
+    if (!p) return perr(PG_EINVAL, "program is NULL");
+    pg_status st = check_view(p, a);
+    if (st) return st;
+    if (n_out < 0 || n_out >= (1LL << 31) || !offsets)
+        return perr(PG_EINVAL, "n_out out of range or offsets NULL");
+    Op op;
+    op.kind = P_BCAST;
+    op.n = n_out;
+    op.a = a;
+    op.offs = offsets;
+    op.n_seg = p->ops[(size_t)a].n;
+    return add_view(p, op, view);
+}
+
 pg_status pg_prog_sum(pg_prog p, int32_t a) {
     clear_error();
     if (!p) return perr(PG_EINVAL, "program is NULL");
@@ -447,7 +483,7 @@ pg_status pg_prog_plan(pg_prog p, size_t* workspace_bytes) {
     }
     for (int32_t v = 0; v < nv; ++v) {
         const Op& op = ops[(size_t)v];
-        if (op.live && !op.fused && (op.kind == P_STENCIL || op.kind == P_GATHER || op.kind == P_SCAN))
+        if (op.live && !op.fused && !pointwise(op.kind) && op.kind != P_INPUT && op.kind != P_CONST)
             p->sched.push_back(Item{false, v, v});
     }
     std::sort(p->sched.begin(), p->sched.end(),
@@ -575,6 +611,14 @@ pg_status pg_prog_bind_workspace(pg_prog p, void* ws, size_t bytes) {
     int32_t hflag = 0;
     PG_HIP(hipMemcpy(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost));
     if (hflag) return perr(PG_ERANGE, "a gather's connectivity has an entry outside its operand");
+    // Segment offsets must start at 0, not decrease and end at the summed length.
+    for (const Op& op : p->ops) {
+        if (op.kind != P_SEGSUM && op.kind != P_BCAST) continue;
+        const int64_t total = op.kind == P_SEGSUM ? p->ops[(size_t)op.a].n : op.n;
+        PG_HIP(launch_validate_offsets(op.offs, op.n_seg, total, flag, nullptr));
+    }
+    PG_HIP(hipMemcpy(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost));
+    if (hflag) return perr(PG_ERANGE, "segment offsets are not 0 = o_0 <= ... <= o_n_seg = length");
     // LDS hash rotation of each fused gather's scatter, chosen on sampled workgroups.
     for (Group& g : p->groups) {
         if (g.gather < 0) continue;
@@ -700,6 +744,8 @@ pg_status pg_prog_run(pg_prog p, const double* const* inputs, double* f_out, dou
         d.ab = ops[(size_t)op.a].active ? shd[(size_t)op.a] : nullptr;
         d.accumulate = p->op_acc[(size_t)v] != D_STORE;
         d.scratch = scratch;
+        d.offs = op.offs;
+        d.n_seg = op.n_seg;
         return d;
     };
 

@@ -4,6 +4,8 @@
 // reverse pass instead of reading them from a tape.  Shadows are FP64; a
 // shadow's first contribution in the reverse pass stores, later ones add
 // (the generated code of section 4 zeroes every shadow and adds).
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "elem_tile.hpp"
 #include "launch.hpp"
@@ -175,6 +177,66 @@ hipError_t launch_scan(int64_t n, const double* a, int rev, double* scratch, dou
                        y, accumulate);
     return hipGetLastError();
 }
+
+// ------------------------------------------- segment sum and broadcast
+//
+// One 64-lane wave per segment, four segments per workgroup.  The segment
+// sum reduces lane-strided partial sums with a fixed butterfly
+// (deterministic); its reverse, and the broadcast, write each entry of the
+// segment from the segment's value; the broadcast's reverse is the segment
+// sum of the output shadow.
+
+constexpr int kSegPerBlock = kBS / kWave;
+
+__global__ void __launch_bounds__(kBS)
+k_segsum(int64_t n_seg, const int64_t* __restrict__ offs, const double* __restrict__ a,
+         double* __restrict__ y, int accumulate) {
+    const int64_t s = (int64_t)blockIdx.x * kSegPerBlock + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (s >= n_seg) return;  // whole waves leave together
+    const int64_t b = offs[s], e = offs[s + 1];
+    double t = 0.0;
+    for (int64_t i = b + lane; i < e; i += kWave) t += a[i];
+    t = wave_sum(t);
+    if (lane == 0) {
+        if (accumulate)
+            y[s] += t;
+        else
+            y[s] = t;
+    }
+}
+
+__global__ void __launch_bounds__(kBS)
+k_segbcast(int64_t n_seg, const int64_t* __restrict__ offs, const double* __restrict__ a,
+           double* __restrict__ y, int accumulate) {
+    const int64_t s = (int64_t)blockIdx.x * kSegPerBlock + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    if (s >= n_seg) return;
+    const int64_t b = offs[s], e = offs[s + 1];
+    const double v = a[s];
+    for (int64_t i = b + lane; i < e; i += kWave) {
+        if (accumulate)
+            y[i] += v;
+        else
+            y[i] = v;
+    }
+}
+
+__global__ void __launch_bounds__(kBS)
+k_validate_offsets(const int64_t* __restrict__ offs, int64_t n_seg, int64_t n, int32_t* flag) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int bad = 0;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s <= n_seg; s += stride) {
+        const int64_t o = offs[s];
+        if (s == 0 && o != 0) bad = 1;
+        if (s == n_seg && o != n) bad = 1;
+        if (s < n_seg && offs[s + 1] < o) bad = 1;
+        if (o < 0 || o > n) bad = 1;
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+inline unsigned seg_blocks(int64_t n_seg) { return (unsigned)((n_seg + kSegPerBlock - 1) / kSegPerBlock); }
 
 // ------------------------------------------------------------ fused groups
 
@@ -407,22 +469,42 @@ hipError_t launch_prog_fwd(const ProgOpDev& o, hipStream_t s) {
         case P_STENCIL: hipLaunchKernelGGL(k_stencil, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.a, o.taps, o.y); break;
         case P_GATHER: hipLaunchKernelGGL(k_gather, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.k, o.conn, o.B, o.a, o.y); break;
         case P_SCAN: return launch_scan(o.n, o.a, 0, o.scratch, o.y, 0, s);
+        case P_SEGSUM:
+            hipLaunchKernelGGL(k_segsum, dim3(seg_blocks(o.n_seg)), dim3(kBS), 0, s, o.n_seg, o.offs, o.a, o.y, 0);
+            break;
+        case P_BCAST:
+            hipLaunchKernelGGL(k_segbcast, dim3(seg_blocks(o.n_seg)), dim3(kBS), 0, s, o.n_seg, o.offs, o.a, o.y, 0);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_prog_rev(const ProgOpDev& o, hipStream_t s) {
-    if (o.n == 0) return hipSuccess;
+    // a broadcast's reverse writes every segment's adjoint, even with no outputs
+    if (o.kind == P_BCAST ? o.n_seg == 0 : o.n == 0) return hipSuccess;
     switch (o.kind) {
         case P_STENCIL: hipLaunchKernelGGL(k_r_stencil, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.yb, o.taps, o.ab, o.accumulate); break;
         case P_GATHER: hipLaunchKernelGGL(k_r_gather, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.k, o.conn, o.B, o.yb, o.ab); break;
         case P_SCAN: return launch_scan(o.n, o.yb, 1, o.scratch, o.ab, o.accumulate, s);
+        case P_SEGSUM:  // reverse of a segment sum: broadcast of the output shadow
+            hipLaunchKernelGGL(k_segbcast, dim3(seg_blocks(o.n_seg)), dim3(kBS), 0, s, o.n_seg, o.offs, o.yb, o.ab, o.accumulate);
+            break;
+        case P_BCAST:  // reverse of a broadcast: segment sum of the output shadow
+            hipLaunchKernelGGL(k_segsum, dim3(seg_blocks(o.n_seg)), dim3(kBS), 0, s, o.n_seg, o.offs, o.yb, o.ab, o.accumulate);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 int64_t prog_scan_chunks(int64_t n) { return (n + kScanItems - 1) / kScanItems; }
+
+hipError_t launch_validate_offsets(const int64_t* offs, int64_t n_seg, int64_t n, int32_t* flag,
+                                   hipStream_t s) {
+    const int64_t g = std::min<int64_t>((n_seg + kBS) / kBS, 4096);
+    hipLaunchKernelGGL(k_validate_offsets, dim3((unsigned)g), dim3(kBS), 0, s, offs, n_seg, n, flag);
+    return hipGetLastError();
+}
 
 }  // namespace pg

@@ -295,3 +295,43 @@ def program_mix(n: int, n_elems: int, k: int, seed: int = 5, hot: int = 0) -> Pr
         ("sum", 17),
     ]
     return ProgramCase(spec, [x, y], f"mix{n}x{n_elems}x{k}" + (f"hot{hot}" if hot else ""))
+
+
+def segment_offsets(n_seg: int, mean_len: float, seed: int, empty_frac: float = 0.1,
+                    long_every: int = 97) -> np.ndarray:
+    """Segment offsets (int64, n_seg + 1 entries): lengths ~ Poisson(mean_len),
+    about `empty_frac` of the segments empty (and the middle one always),
+    every `long_every`-th segment ten times longer (so one wave loops
+    several times)."""
+    rng = np.random.default_rng(seed)
+    lens = rng.poisson(mean_len, n_seg)
+    lens[rng.uniform(size=n_seg) < empty_frac] = 0
+    lens[::long_every] *= 10
+    if n_seg >= 3:
+        lens[n_seg // 2] = 0  # at least one empty segment
+    return np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+
+
+def program_segments(n_seg: int = 1000, mean_len: float = 20.0, seed: int = 6) -> ProgramCase:
+    """Segment sums and broadcasts with active and inactive operands:
+    f = sum(x * bcast(psi(segsum(x)))) + sum(scale(segsum(x * c)))."""
+    off = segment_offsets(n_seg, mean_len, seed)
+    n = int(off[-1])
+    rng = np.random.default_rng(seed + 1)
+    x = rng.uniform(-1.0, 1.0, n)
+    c = rng.uniform(-1.0, 1.0, n)
+    spec = [
+        ("input", n),              # 0 x
+        ("segsum", 0, off),        # 1 per-segment sums
+        ("map", 1, "psi"),         # 2
+        ("bcast", 2, off),         # 3 back to entries
+        ("mul", 3, 0),             # 4
+        ("const", c),              # 5
+        ("mul", 0, 5),             # 6
+        ("segsum", 6, off),        # 7
+        ("scale", 7, 0.5),         # 8
+        ("bcast", 8, off),         # 9
+        ("add", 4, 1.0, 9, 1.0),   # 10
+        ("sum", 10),
+    ]
+    return ProgramCase(spec, [x], f"segments{n_seg}")

@@ -37,6 +37,7 @@ EXPORTS = ("pg_default_options", "pg_mesh_plan", "pg_dense_plan", "pg_bdense_pla
            "pg_plan_destroy", "pg_last_error", "pg_version",
            "pg_prog_create", "pg_prog_input", "pg_prog_const", "pg_prog_scale", "pg_prog_stencil",
            "pg_prog_gather", "pg_prog_add", "pg_prog_mul", "pg_prog_map", "pg_prog_scan",
+           "pg_prog_segment_sum", "pg_prog_broadcast",
            "pg_prog_sum", "pg_prog_fusion", "pg_prog_plan", "pg_prog_bind_workspace", "pg_prog_run",
            "pg_prog_info", "pg_prog_destroy")
 MAPS = {"square": 0, "psi": 1}
@@ -118,6 +119,8 @@ def lib():
     L.pg_prog_mul.argtypes = [_VP, _I32, _I32, I32P]
     L.pg_prog_map.argtypes = [_VP, _I32, ctypes.c_int, I32P]
     L.pg_prog_scan.argtypes = [_VP, _I32, I32P]
+    L.pg_prog_segment_sum.argtypes = [_VP, _I32, _I64, _VP, I32P]
+    L.pg_prog_broadcast.argtypes = [_VP, _I32, _VP, _I64, I32P]
     L.pg_prog_sum.argtypes = [_VP, _I32]
     L.pg_prog_plan.argtypes = [_VP, _SZP]
     L.pg_prog_bind_workspace.argtypes = [_VP, _VP, ctypes.c_size_t]
@@ -455,7 +458,8 @@ class Program:
         """Build (not plan) a program from construct tuples: ("input", n),
         ("const", data), ("scale", a, alpha), ("stencil", a, offsets, coeffs),
         ("gather", a, conn, B), ("add", a, alpha, b, beta), ("mul", a, b),
-        ("map", a, fn), ("scan", a), ("sum", a); array operands (NumPy or
+        ("map", a, fn), ("scan", a), ("segsum", a, offsets), ("bcast", a,
+        offsets), ("sum", a); array operands (NumPy or
         torch) are copied to the device."""
         p = cls(fusion)
 
@@ -483,6 +487,10 @@ class Program:
                 p.map(op[1], op[2])
             elif k == "scan":
                 p.scan(op[1])
+            elif k == "segsum":
+                p.segment_sum(op[1], dev(op[2], torch.int64))
+            elif k == "bcast":
+                p.broadcast(op[1], dev(op[2], torch.int64), int(op[2][-1]))
             elif k == "sum":
                 p.sum(op[1])
             else:
@@ -539,6 +547,27 @@ class Program:
 
     def scan(self, a: int) -> int:
         return self._view(lib().pg_prog_scan, "pg_prog_scan", int(a))
+
+    def segment_sum(self, a: int, offsets: torch.Tensor) -> int:
+        """y_s = sum of view a over [offsets[s], offsets[s+1]) (int64 offsets)."""
+        _need_cuda(offsets)
+        if offsets.dtype != torch.int64 or offsets.dim() != 1 or offsets.numel() < 1:
+            raise PgError(EDTYPE, "segment_sum", "offsets: 1-D int64 with n_seg + 1 entries")
+        self._keep.append(offsets)
+        return self._view(lib().pg_prog_segment_sum, "pg_prog_segment_sum", int(a),
+                          offsets.numel() - 1, _ptr(offsets))
+
+    def broadcast(self, a: int, offsets: torch.Tensor, n_out: Optional[int] = None) -> int:
+        """y_i = a_s for offsets[s] <= i < offsets[s+1]; n_out = offsets[-1]
+        (read from the device when not given)."""
+        _need_cuda(offsets)
+        if offsets.dtype != torch.int64 or offsets.dim() != 1 or offsets.numel() < 1:
+            raise PgError(EDTYPE, "broadcast", "offsets: 1-D int64 with len(a) + 1 entries")
+        if n_out is None:
+            n_out = int(offsets[-1].item())
+        self._keep.append(offsets)
+        return self._view(lib().pg_prog_broadcast, "pg_prog_broadcast", int(a), _ptr(offsets),
+                          int(n_out))
 
     def sum(self, a: int) -> None:
         check(lib().pg_prog_sum(self._p, int(a)), "pg_prog_sum")

@@ -188,3 +188,34 @@ def test_self_add_and_shared_leaf(fusion):
             ("stencil", 3, [0, -1], [1.0, 0.5]), ("add", 4, 1.0, 3, 1.0), ("mul", 5, 0),
             ("sum", 6)]
     check_case(inputs.ProgramCase(spec, [x, y], "self-add"), fusion)
+
+
+@pytest.mark.parametrize("fusion", FUSION)
+@pytest.mark.parametrize("n_seg,mean", [(1000, 20.0), (37, 300.0), (5, 0.5)])
+def test_segment_sum_and_broadcast(n_seg, mean, fusion):
+    check_case(inputs.program_segments(n_seg, mean, seed=21), fusion)
+
+
+def test_segment_offsets_are_checked_at_bind():
+    off = np.array([0, 3, 2, 5], dtype=np.int64)          # decreasing
+    spec = [("input", 5), ("segsum", 0, off), ("sum", 1)]
+    with pytest.raises(P.PgError) as e:
+        P.Program.from_spec(spec).plan()
+    assert e.value.code == P.ERANGE
+    off = np.array([0, 2, 4], dtype=np.int64)             # ends short of the input
+    spec = [("input", 5), ("segsum", 0, off), ("sum", 1)]
+    with pytest.raises(P.PgError) as e:
+        P.Program.from_spec(spec).plan()
+    assert e.value.code == P.ERANGE
+
+
+@pytest.mark.parametrize("fusion", FUSION)
+def test_broadcast_with_no_outputs(fusion):
+    # every segment empty: the broadcast has no outputs, yet its reverse must
+    # still define the adjoint of each segment (zero)
+    off = np.zeros(4, dtype=np.int64)
+    x = _rand(3, 9)
+    spec = [("input", 3), ("bcast", 0, off), ("sum", 1)]
+    prog, (f, (g,)) = run_case(inputs.ProgramCase(spec, [x], "empty-bcast"), fusion=fusion)
+    assert f.item() == 0.0
+    assert torch.equal(g.cpu(), torch.zeros(3, dtype=torch.float64))

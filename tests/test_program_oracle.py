@@ -96,3 +96,27 @@ def test_psi_map_matches_oracle_psi(orc):
     assert rel(vals[1], orc.psi(s)) < 1e-15
     _, (g,) = OP.gradient(spec, [s])
     assert rel(g, orc.dpsi(s)) < 1e-15
+
+
+def test_segments_complex_step():
+    case = inputs.program_segments(9, 3.0, seed=13)
+    assert (np.diff(case.spec[1][2]) == 0).any()      # an empty segment is present
+    _, (g,) = OP.gradient(case.spec, case.inputs)
+    cs = np.array([OP.complex_step(case.spec, case.inputs, 0, j) for j in range(case.inputs[0].size)])
+    assert rel(g, cs) < 1e-13
+
+
+def test_broadcast_of_segment_sum_closed_form():
+    off = inputs.segment_offsets(12, 4.0, seed=14)
+    n = int(off[-1])
+    rng = np.random.default_rng(15)
+    x, w = rng.uniform(-1, 1, n), rng.uniform(0.5, 1.5, n)
+    spec = [("input", n), ("segsum", 0, off), ("bcast", 1, off), ("const", w), ("mul", 2, 3),
+            ("sum", 4)]
+    f, (g,) = OP.gradient(spec, [x])
+    seg = np.repeat(np.arange(12), np.diff(off))
+    sx = np.bincount(seg, weights=x, minlength=12)
+    sw = np.bincount(seg, weights=w, minlength=12)
+    # f = sum_i w_i * (sum of x over i's segment); df/dx_i = sum of w over i's segment
+    assert srel(f, float(w @ sx[seg])) < 1e-14
+    assert rel(g, sw[seg]) < 1e-14
