@@ -69,6 +69,7 @@ bool pointwise(int kind) { return kind == P_SCALE || kind == P_ADD || kind == P_
 struct Group {
     std::vector<int32_t> members, leaves;
     int32_t gather = -1;  // fused gather view (one of the leaves)
+    bool export_gather = false;  // a gather of its own: no ops, its value written out
     bool sealed = false, has_sum = false;
     int32_t pos = 0;      // schedule position: its last member (the end for a sum-only group)
     uint32_t hash_shift = 2533;
@@ -473,17 +474,29 @@ pg_status pg_prog_plan(pg_prog p, size_t* workspace_bytes) {
             op.fused = true;
         }
     }
+    // Every other gather runs in a group of its own that writes its value out,
+    // so it gets the same row loads and LDS-combined reverse scatter.
+    for (int32_t v = 0; v < nv; ++v) {
+        const Op& op = ops[(size_t)v];
+        if (!op.live || op.kind != P_GATHER || op.fused) continue;
+        G.emplace_back();
+        G.back().leaves.push_back(v);
+        G.back().gather = v;
+        G.back().export_gather = true;
+        G.back().pos = v;
+    }
     // Forward schedule.
     p->sched.clear();
     for (size_t gi = 0; gi < G.size(); ++gi) {
         Group& g = G[gi];
-        if (g.members.empty() && !g.has_sum) continue;  // merged away
+        if (g.members.empty() && !g.has_sum && g.gather < 0) continue;  // merged away
         if (!g.members.empty()) g.pos = g.members.back();
         p->sched.push_back(Item{true, (int32_t)gi, g.pos});
     }
     for (int32_t v = 0; v < nv; ++v) {
         const Op& op = ops[(size_t)v];
-        if (op.live && !op.fused && !pointwise(op.kind) && op.kind != P_INPUT && op.kind != P_CONST)
+        if (op.live && op.kind != P_GATHER && !pointwise(op.kind) && op.kind != P_INPUT &&
+            op.kind != P_CONST)
             p->sched.push_back(Item{false, v, v});
     }
     std::sort(p->sched.begin(), p->sched.end(),
@@ -525,7 +538,7 @@ pg_status pg_prog_plan(pg_prog p, size_t* workspace_bytes) {
         } else {
             const Op& op = ops[(size_t)it.id];
             if (!op.active) continue;
-            p->op_acc[(size_t)it.id] = deliver(op.a, op.kind == P_GATHER);
+            p->op_acc[(size_t)it.id] = deliver(op.a, false);
         }
     }
     for (int32_t v = 0; v < nv; ++v)
@@ -571,7 +584,7 @@ pg_status pg_prog_plan(pg_prog p, size_t* workspace_bytes) {
             for (int32_t u : g.leaves) rev = rev || (u != g.gather && ops[(size_t)u].active);
             if (rev && !(p->fusion && g.has_sum)) ++st.rev_kernels;
             if (g.gather >= 0) {
-                ++st.fused_gathers;
+                if (!g.export_gather) ++st.fused_gathers;
                 if (ops[(size_t)ops[(size_t)g.gather].a].active) ++st.atomic_ops;
             }
         } else {
@@ -580,7 +593,6 @@ pg_status pg_prog_plan(pg_prog p, size_t* workspace_bytes) {
             st.fwd_kernels += nk;
             if (!op.active) continue;
             st.rev_kernels += nk;
-            if (op.kind == P_GATHER) ++st.atomic_ops;
             if (op.kind == P_STENCIL && op.taps.n > 1) ++st.rescheduled_ops;
         }
     }
@@ -726,6 +738,12 @@ pg_status pg_prog_run(pg_prog p, const double* const* inputs, double* f_out, dou
             d.gsrc = val[(size_t)go.a];
             d.gsrc_shadow = ops[(size_t)go.a].active ? shd[(size_t)go.a] : nullptr;
             d.hash_shift = g.hash_shift;
+            if (g.export_gather) {
+                d.export_slot[d.n_exports] = d.gather_slot;
+                d.export_val[d.n_exports] = at(p, go.val_off);
+                d.export_shadow[d.n_exports] = go.active ? shd[(size_t)g.gather] : nullptr;
+                ++d.n_exports;
+            }
         }
         return d;
     };

@@ -37,16 +37,6 @@ k_stencil(int64_t n, const double* __restrict__ a, ProgTaps taps, double* __rest
     y[i] = s;
 }
 
-__global__ void __launch_bounds__(kBS)
-k_gather(int64_t E, int32_t k, const int32_t* __restrict__ conn, const double* __restrict__ B,
-         const double* __restrict__ a, double* __restrict__ y) {
-    const int64_t e = (int64_t)blockIdx.x * kBS + threadIdx.x;
-    if (e >= E) return;
-    double s = 0.0;
-    for (int j = 0; j < k; ++j) s += B[e * k + j] * a[conn[e * k + j]];
-    y[e] = s;
-}
-
 // ---------------------------------------------------------- reverse pass
 
 // The reverse of a stencil reads ybar through several index expressions; it
@@ -65,16 +55,6 @@ k_r_stencil(int64_t n, const double* __restrict__ yb, ProgTaps taps, double* __r
         ab[j] += s;
     else
         ab[j] = s;
-}
-
-// The reverse of a gather writes through an index that is a view entry: atomic.
-__global__ void __launch_bounds__(kBS)
-k_r_gather(int64_t E, int32_t k, const int32_t* __restrict__ conn, const double* __restrict__ B,
-           const double* __restrict__ yb, double* __restrict__ ab) {
-    const int64_t e = (int64_t)blockIdx.x * kBS + threadIdx.x;
-    if (e >= E) return;
-    const double v = yb[e];
-    for (int j = 0; j < k; ++j) atomic_add_f64(ab + conn[e * k + j], B[e * k + j] * v);
 }
 
 // ------------------------------------------------------------ prefix scan
@@ -310,6 +290,9 @@ __global__ void __launch_bounds__(BS) k_group(GroupDev g) {
     const int L = g.n_leaves;
     Slots<NS> r;
     GatherRow<K> row;
+    // The reverse of a group without ops (a gather of its own) is linear: it
+    // needs the gather rows but no forward values.
+    const bool values = FWD || g.n_ops > 0;
     if (ok) {
         // Every load first: the gather row, the leaves, then the gathered entries.
         if constexpr (K > 0) {
@@ -319,7 +302,8 @@ __global__ void __launch_bounds__(BS) k_group(GroupDev g) {
 #pragma unroll
         for (int l = 0; l < NL; ++l)
             if (l < L && l != g.gather_slot) r.r[l] = g.leaf[l][i];
-        if constexpr (K > 0) {
+        if (!values) {
+        } else if constexpr (K > 0) {
             double xv[K];
 #pragma unroll
             for (int j = 0; j < K; ++j) xv[j] = g.gsrc[row.c[j]];
@@ -332,6 +316,7 @@ __global__ void __launch_bounds__(BS) k_group(GroupDev g) {
             for (int j = 0; j < g.gk; ++j) u += g.gB[i * g.gk + j] * g.gsrc[g.gconn[i * g.gk + j]];
             r.set(g.gather_slot, u);
         }
+        (void)values;
         for (int j = 0; j < g.n_ops; ++j) {
             const GOp o = g.ops[j];
             const double x = r.get(o.a);
@@ -467,7 +452,6 @@ hipError_t launch_prog_fwd(const ProgOpDev& o, hipStream_t s) {
     if (o.n == 0) return hipSuccess;
     switch (o.kind) {
         case P_STENCIL: hipLaunchKernelGGL(k_stencil, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.a, o.taps, o.y); break;
-        case P_GATHER: hipLaunchKernelGGL(k_gather, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.k, o.conn, o.B, o.a, o.y); break;
         case P_SCAN: return launch_scan(o.n, o.a, 0, o.scratch, o.y, 0, s);
         case P_SEGSUM:
             hipLaunchKernelGGL(k_segsum, dim3(seg_blocks(o.n_seg)), dim3(kBS), 0, s, o.n_seg, o.offs, o.a, o.y, 0);
@@ -485,7 +469,6 @@ hipError_t launch_prog_rev(const ProgOpDev& o, hipStream_t s) {
     if (o.kind == P_BCAST ? o.n_seg == 0 : o.n == 0) return hipSuccess;
     switch (o.kind) {
         case P_STENCIL: hipLaunchKernelGGL(k_r_stencil, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.yb, o.taps, o.ab, o.accumulate); break;
-        case P_GATHER: hipLaunchKernelGGL(k_r_gather, dim3(nblocks(o.n)), dim3(kBS), 0, s, o.n, o.k, o.conn, o.B, o.yb, o.ab); break;
         case P_SCAN: return launch_scan(o.n, o.yb, 1, o.scratch, o.ab, o.accumulate, s);
         case P_SEGSUM:  // reverse of a segment sum: broadcast of the output shadow
             hipLaunchKernelGGL(k_segbcast, dim3(seg_blocks(o.n_seg)), dim3(kBS), 0, s, o.n_seg, o.offs, o.yb, o.ab, o.accumulate);

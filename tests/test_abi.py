@@ -215,8 +215,8 @@ def test_program_plan_reports_the_generated_reverse_pass():
     assert L.pg_prog_info(p, ctypes.byref(st)) == P.OK
     # Groups: {a} (sealed when the gather g reads it), {m} (sealed by the scan),
     # {q + sum}.  The gather g is read only by group {m} and runs inside it;
-    # gc, read by the same group, stays a kernel of its own.
-    assert st.groups == 3 and st.fused_gathers == 1 and st.dead_ops == 0
+    # gc, read by the same group, runs in a group of its own.
+    assert st.groups == 4 and st.fused_gathers == 1 and st.dead_ops == 0
     # forward: s1, s2, gc, the scan's 3, three groups, the final reduction
     assert st.fwd_kernels == 3 + 3 + 3 + 1
     # reverse: s1, the scan's 3, groups {a} and {m}; inactive s2 and gc have
@@ -262,10 +262,11 @@ def test_mesh_program_plan(fusion):
         assert (st.groups, st.fused_gathers, st.fwd_kernels, st.rev_kernels) == (1, 1, 2, 0)
         assert st.tape_bytes == 0
     else:
-        # one kernel per construct (the sum's partials taken by the mul kernel),
-        # then the final reduction; reverse: mul (seeded), map, the gather's
-        # atomic scatter; recorded: the gather's and the map's outputs
-        assert (st.groups, st.fused_gathers, st.fwd_kernels, st.rev_kernels) == (2, 0, 4, 3)
+        # one kernel per construct (the gather in a group of its own, the sum's
+        # partials taken by the mul kernel), then the final reduction; reverse:
+        # mul (seeded), map, the gather's atomic scatter; recorded: the
+        # gather's and the map's outputs
+        assert (st.groups, st.fused_gathers, st.fwd_kernels, st.rev_kernels) == (3, 0, 4, 3)
         assert st.tape_bytes == 8 * 2 * 400
     L.pg_prog_destroy(p)
 
