@@ -320,11 +320,16 @@ pg_status pg_prog_destroy(pg_prog prog);
 /* Measurement hook.  mode 0: off; 1: time the dominant kernel of every
  * subsequent evaluation (the element pass of a mesh or batch, the fused row
  * pass of a dense plan, the forward or backward product of a batched dense
- * plan); 2: time each whole evaluation call.  Each timed launch records a
- * pair of HIP events (owned by the plan, up to 4096 pairs) on the call's
- * stream.  pg_timing_read waits for the last recorded event, returns the sum
- * of the elapsed times (milliseconds, host out) and the number of timed
- * launches (host out), and clears the record.  Enabling resets the record. */
+ * plan, the pass of the section 4 example); 2: time each whole evaluation
+ * call.  In mode 1 a single dominant kernel is launched with
+ * hipExtLaunchKernelGGL, which stamps a pair of HIP events with the
+ * kernel's own start and end; phases of several kernels (the colour
+ * passes, the gather variant, the dense row/column fallback) and mode 2 are
+ * bracketed by events recorded on the call's stream.  Events are owned by
+ * the plan (up to 4096 pairs).  pg_timing_read waits for the last recorded
+ * event, returns the sum of the elapsed times (milliseconds, host out) and
+ * the number of timed launches (host out), and clears the record.
+ * Enabling resets the record. */
 pg_status pg_timing(pg_plan plan, int32_t mode);
 pg_status pg_timing_read(pg_plan plan, double* total_ms, int64_t* count);
 

@@ -323,6 +323,25 @@ pg_status need_bound(pg_plan p) {
 constexpr int64_t kMaxTimed = 4096;
 
 // Record the start (or stop) event of a timed launch at this level.
+// Timing of one dominant kernel: arms the plan's next event pair for the
+// next PG_LAUNCH, which stamps it with the kernel's own start and end; the
+// pair counts only if a launch took it (an empty input launches nothing).
+hipError_t tkern(pg_plan p, bool start) {
+    if (p->timing_mode != 1 || p->ev_n >= kMaxTimed) return hipSuccess;
+    LaunchEvents& a = armed_launch_events();
+    if (start) {
+        a.start = p->ev[2 * p->ev_n];
+        a.stop = p->ev[2 * p->ev_n + 1];
+    } else if (a.start == nullptr) {
+        ++p->ev_n;
+    } else {
+        a = LaunchEvents{};
+    }
+    return hipSuccess;
+}
+
+// Timing of a range of launches (several kernels, or a whole call): events
+// recorded on the stream around it.
 hipError_t tmark(pg_plan p, int level, bool start, hipStream_t s) {
     if (p->timing_mode != level || p->ev_n >= kMaxTimed) return hipSuccess;
     hipError_t e = hipEventRecord(p->ev[2 * p->ev_n + (start ? 0 : 1)], s);
@@ -403,9 +422,9 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
     const bool grd = (want & W_GRAD) != 0;
     if (!grd) {
         q.u_store = p->at<double>(p->o_u);
-        PG_HIP(tmark(p, 1, true, s));
+        PG_HIP(tkern(p, true));
         PG_HIP(launch_mesh_elem(m, M_PRIMAL, q, s));
-        PG_HIP(tmark(p, 1, false, s));
+        PG_HIP(tkern(p, false));
         if (f_out) PG_HIP(launch_final_sum(q.partials, p->mesh_blocks_n, f_out, s));
         if (q.u_store) {
             p->tape_valid = true;
@@ -455,9 +474,9 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
             q.gacc = static_cast<double*>(grad);
             if (!acc) PG_HIP(launch_zero(grad, sizeof(double) * (size_t)m.n_nodes, s));
         }
-        PG_HIP(tmark(p, 1, true, s));
+        PG_HIP(tkern(p, true));
         PG_HIP(launch_mesh_elem(m, obj ? M_GRAD_ATOMIC : M_ADJ_ATOMIC, q, s));
-        PG_HIP(tmark(p, 1, false, s));
+        PG_HIP(tkern(p, false));
         if (f32)
             PG_HIP(launch_f64_to_f32(q.gacc, static_cast<float*>(grad), m.n_nodes, acc, s));
         if (obj && f_out) PG_HIP(launch_final_sum(q.partials, p->mesh_blocks_n, f_out, s));
@@ -655,9 +674,9 @@ pg_status batch_run(pg_plan p, const void* x, const double* fbar, void* grad, do
     q.fbar = fbar;
     if (!grd) {
         q.u_store = p->at<double>(p->o_u);
-        PG_HIP(tmark(p, 1, true, s));
+        PG_HIP(tkern(p, true));
         PG_HIP(launch_batch_persistent(p->batch, B_PRIMAL, q, s));
-        PG_HIP(tmark(p, 1, false, s));
+        PG_HIP(tkern(p, false));
         if (f_out) PG_HIP(launch_segmented_sum(q.partials, seg, ni, f_out, s));
         if (q.u_store) {
             p->tape_valid = true;
@@ -676,9 +695,9 @@ pg_status batch_run(pg_plan p, const void* x, const double* fbar, void* grad, do
         q.grad = grad;
         if (!acc) PG_HIP(launch_zero(grad, sizeof(double) * (size_t)p->n_nodes_total, s));
     }
-    PG_HIP(tmark(p, 1, true, s));
+    PG_HIP(tkern(p, true));
     PG_HIP(launch_batch_persistent(p->batch, obj ? B_GRAD_ATOMIC : B_ADJ_ATOMIC, q, s));
-    PG_HIP(tmark(p, 1, false, s));
+    PG_HIP(tkern(p, false));
     if (f32)
         PG_HIP(launch_f64_to_f32((const double*)q.grad, static_cast<float*>(grad),
                                  p->n_nodes_total, acc, s));
@@ -703,10 +722,10 @@ pg_status dense_run(pg_plan p, const void* x, const double* fbar, void* grad, do
     }
     // The fused kernel reads x with 16-byte vector loads.
     if (p->dense_fused && ((uintptr_t)x % 16) == 0) {
-        PG_HIP(tmark(p, 1, true, s));
+        PG_HIP(tkern(p, true));
         PG_HIP(launch_dense_fused(d, x, fbar, grd ? 1 : 0, partials, p->at<double>(p->o_colpart),
                                   p->dense_groups, s));
-        PG_HIP(tmark(p, 1, false, s));
+        PG_HIP(tkern(p, false));
         if (grd)
             PG_HIP(launch_dense_colsum(p->at<double>(p->o_colpart), p->dense_groups, d.cols, grad,
                                        dt, p->opt.accumulate, s));
@@ -732,9 +751,9 @@ pg_status bdense_run(pg_plan p, const void* X, const double* fbar, void* G, doub
     const bool obj = (want & W_OBJ) != 0;
     if (!grd) {
         const bool store = p->opt.ckpt == PG_STORE;
-        PG_HIP(tmark(p, 1, true, s));
+        PG_HIP(tkern(p, true));
         PG_HIP(launch_bdense_fwd(p->bd, X, partials, store ? V : nullptr, s));
-        PG_HIP(tmark(p, 1, false, s));
+        PG_HIP(tkern(p, false));
         if (f_out) PG_HIP(launch_final_sum(partials, p->bd_tiles, f_out, s));
         if (store) {
             p->tape_valid = true;
@@ -748,9 +767,9 @@ pg_status bdense_run(pg_plan p, const void* X, const double* fbar, void* G, doub
     } else if (!p->tape_valid) {
         return fail(PG_ESTATE, "no stored forward values: call pg_objective first");
     }
-    PG_HIP(tmark(p, 1, true, s));
+    PG_HIP(tkern(p, true));
     PG_HIP(launch_bdense_bwd(p->bd, V, fbar, G, p->opt.accumulate, s));
-    PG_HIP(tmark(p, 1, false, s));
+    PG_HIP(tkern(p, false));
     return PG_OK;
 }
 
@@ -1023,6 +1042,7 @@ pg_status pg_timing(pg_plan p, int32_t mode) {
     }
     p->timing_mode = mode;
     p->ev_n = 0;
+    armed_launch_events() = LaunchEvents{};
     return PG_OK;
 }
 
@@ -1091,9 +1111,9 @@ pg_status pg_laplace1d_objective(pg_plan p, const void* x, const void* b, double
     double* partials = p->at<double>(p->o_partials);
     const Dtype dt = p->dtype == PG_F64 ? F64 : F32;
     PG_HIP(tmark(p, 2, true, s));
-    PG_HIP(tmark(p, 1, true, s));
+    PG_HIP(tkern(p, true));
     PG_HIP(launch_laplace1d(p->lap_n, dt, 0, x, b, nullptr, nullptr, nullptr, nullptr, partials, 0, s));
-    PG_HIP(tmark(p, 1, false, s));
+    PG_HIP(tkern(p, false));
     PG_HIP(launch_final_sum(partials, laplace1d_blocks(p->lap_n), f_out, s));
     PG_HIP(tmark(p, 2, false, s));
     return PG_OK;
@@ -1125,14 +1145,14 @@ pg_status pg_laplace1d_gradient(pg_plan p, const void* x, const void* b, void* g
             g64 = dt == F64 ? static_cast<double*>(gx) : p->at<double>(p->o_gacc);
             if (dt == F32 || !acc) PG_HIP(launch_zero(g64, sizeof(double) * (size_t)p->lap_n, s));
         }
-        PG_HIP(tmark(p, 1, true, s));
+        PG_HIP(tkern(p, true));
         PG_HIP(launch_laplace1d(p->lap_n, dt, 2, x, b, g64, nullptr, gb, nullptr, partials, acc, s));
-        PG_HIP(tmark(p, 1, false, s));
+        PG_HIP(tkern(p, false));
         if (gx && dt == F32) PG_HIP(launch_f64_to_f32(g64, static_cast<float*>(gx), p->lap_n, acc, s));
     } else {
-        PG_HIP(tmark(p, 1, true, s));
+        PG_HIP(tkern(p, true));
         PG_HIP(launch_laplace1d(p->lap_n, dt, 1, x, b, nullptr, gx, gb, nullptr, partials, acc, s));
-        PG_HIP(tmark(p, 1, false, s));
+        PG_HIP(tkern(p, false));
     }
     if (f_out) PG_HIP(launch_final_sum(partials, laplace1d_blocks(p->lap_n), f_out, s));
     PG_HIP(tmark(p, 2, false, s));
@@ -1158,6 +1178,10 @@ pg_status pg_jvp(pg_plan p, const void* x, const void* d, double* jvp_out, pg_st
 
 pg_status pg_plan_destroy(pg_plan p) {
     if (p) {
+        // A launch that failed after arming leaves the pair armed: drop it.
+        LaunchEvents& a = armed_launch_events();
+        for (auto& e : p->ev)
+            if (a.start == e || a.stop == e) a = LaunchEvents{};
         for (auto& e : p->ev) (void)hipEventDestroy(e);
     }
     delete p;

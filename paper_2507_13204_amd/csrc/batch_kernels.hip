@@ -116,18 +116,18 @@ hipError_t launch_agg(const BatchView& b, const BatchPass& p, hipStream_t s) {
             TileArgs a{b.conn, b.B, b.w, p.x, nullptr, p.u_in, nullptr, nullptr,
                        static_cast<double*>(p.grad), nullptr, 0u};
             auto kern = k_atomic_persistent<T, K, MODE, BatchTiles>;
-            hipLaunchKernelGGL(kern, dim3(resident_grid(kern, p.block, b.n_tiles, p.grid)),
+            PG_LAUNCH(kern, dim3(resident_grid(kern, p.block, b.n_tiles, p.grid)),
                                dim3(p.block), 0, s, tiles, a, p.fbar, 1, p.partials);
             return hipGetLastError();
         }
     }
     if (agg) {
         auto kern = k_batch_persistent<T, K, MODE, EPT, true>;
-        hipLaunchKernelGGL(kern, dim3(resident_grid(kern, p.block, b.n_tiles, p.grid)),
+        PG_LAUNCH(kern, dim3(resident_grid(kern, p.block, b.n_tiles, p.grid)),
                            dim3(p.block), 0, s, b, p);
     } else {
         auto kern = k_batch_persistent<T, K, MODE, EPT, false>;
-        hipLaunchKernelGGL(kern, dim3(resident_grid(kern, p.block, b.n_tiles, p.grid)),
+        PG_LAUNCH(kern, dim3(resident_grid(kern, p.block, b.n_tiles, p.grid)),
                            dim3(p.block), 0, s, b, p);
     }
     return hipGetLastError();
@@ -153,7 +153,7 @@ hipError_t launch_k(const BatchView& b, const BatchPass& p, hipStream_t s) {
             if (b.tile_elems != p.block) return hipErrorInvalidValue;
             {
                 auto kern = k_batch_persistent_dyn<T, MODE>;
-                hipLaunchKernelGGL(kern, dim3(resident_grid(kern, p.block, b.n_tiles, p.grid)),
+                PG_LAUNCH(kern, dim3(resident_grid(kern, p.block, b.n_tiles, p.grid)),
                                    dim3(p.block), 0, s, b, p);
             }
             return hipGetLastError();

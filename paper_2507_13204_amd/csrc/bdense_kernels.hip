@@ -263,10 +263,10 @@ template <typename T, bool TRANS, int EPI>
 void launch_gemm(const BDenseView& b, dim3 grid, hipStream_t s, const T* A, const T* Bm, const T* W,
                  double* partials, T* V, const double* fbar, T* G, int accumulate) {
     if (full_tiles(b, Bm))
-        hipLaunchKernelGGL((k_gemm_mfma<T, TRANS, EPI, true>), grid, dim3(NTHR), 0, s, A, Bm, b.m,
+        PG_LAUNCH((k_gemm_mfma<T, TRANS, EPI, true>), grid, dim3(NTHR), 0, s, A, Bm, b.m,
                            b.n, b.m, W, partials, V, fbar, G, accumulate);
     else
-        hipLaunchKernelGGL((k_gemm_mfma<T, TRANS, EPI, false>), grid, dim3(NTHR), 0, s, A, Bm, b.m,
+        PG_LAUNCH((k_gemm_mfma<T, TRANS, EPI, false>), grid, dim3(NTHR), 0, s, A, Bm, b.m,
                            b.n, b.m, W, partials, V, fbar, G, accumulate);
 }
 

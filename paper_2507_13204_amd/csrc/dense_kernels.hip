@@ -212,7 +212,7 @@ hipError_t fused_q(const DenseView& d, const void* x, const double* fbar, int wa
     const T* xp = static_cast<const T*>(x);
 #define PG_FUSED_CASE(QV)                                                                        \
     if (q <= QV) {                                                                               \
-        hipLaunchKernelGGL((k_dense_fused<T, QV>), dim3(ngroups), dim3(kFusedBS), 0, s, d, xp,  \
+        PG_LAUNCH((k_dense_fused<T, QV>), dim3(ngroups), dim3(kFusedBS), 0, s, d, xp,  \
                            fbar, want_grad, partials, colpart, ngroups);                        \
         return hipGetLastError();                                                                \
     }

@@ -71,15 +71,15 @@ hipError_t launch_t(int64_t n, int mode, const void* x, const void* b, double* g
     const T* bp = static_cast<const T*>(b);
     switch (mode) {
         case 0:
-            hipLaunchKernelGGL((k_laplace1d<T, 0>), dim3(nb), dim3(256), 0, s, n, xp, bp, nullptr,
+            PG_LAUNCH((k_laplace1d<T, 0>), dim3(nb), dim3(256), 0, s, n, xp, bp, nullptr,
                                nullptr, nullptr, fbar, partials, accumulate);
             break;
         case 1:
-            hipLaunchKernelGGL((k_laplace1d<T, 1>), dim3(nb), dim3(256), 0, s, n, xp, bp, nullptr,
+            PG_LAUNCH((k_laplace1d<T, 1>), dim3(nb), dim3(256), 0, s, n, xp, bp, nullptr,
                                static_cast<T*>(gx), static_cast<T*>(gb), fbar, partials, accumulate);
             break;
         case 2:
-            hipLaunchKernelGGL((k_laplace1d<T, 2>), dim3(nb), dim3(256), 0, s, n, xp, bp, gx64,
+            PG_LAUNCH((k_laplace1d<T, 2>), dim3(nb), dim3(256), 0, s, n, xp, bp, gx64,
                                nullptr, static_cast<T*>(gb), fbar, partials, accumulate);
             break;
         default: return hipErrorInvalidValue;

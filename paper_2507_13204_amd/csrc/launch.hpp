@@ -1,9 +1,35 @@
 // Internal host-side launchers of the HIP kernels (not part of the C ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
+
+namespace pg {
+
+// Event pair armed by the timing hook for the next dominant-kernel launch.
+// PG_LAUNCH hands it to hipExtLaunchKernelGGL, which stamps the events with
+// the kernel's own start and end (no dispatch gap inside the pair), then
+// disarms it; with nothing armed it is a plain launch.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchEvents& armed_launch_events();
+
+}  // namespace pg
+
+#define PG_LAUNCH(kernel, grid, block, shmem, stream, ...)                                       \
+    do {                                                                                         \
+        ::pg::LaunchEvents& ev_ = ::pg::armed_launch_events();                                   \
+        if (ev_.start) {                                                                         \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, ev_.start, ev_.stop, 0,    \
+                                  __VA_ARGS__);                                                  \
+            ev_ = ::pg::LaunchEvents{};                                                          \
+        } else {                                                                                 \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                 \
+        }                                                                                        \
+    } while (0)
 
 namespace pg {
 

@@ -306,10 +306,10 @@ hipError_t launch_elem_t(const MeshView& m, const MeshPass& p, hipStream_t s) {
     // at worst (all distinct); meshes with locality fill it far less.
     const bool agg = is_atomic(MODE) && p.combine && (int64_t)p.block * EPT * K <= 2 * kAggSlots;
     if (agg)
-        hipLaunchKernelGGL((k_mesh_elem<T, K, MODE, EPT, true>), dim3((unsigned)nb), dim3(p.block), 0,
+        PG_LAUNCH((k_mesh_elem<T, K, MODE, EPT, true>), dim3((unsigned)nb), dim3(p.block), 0,
                            s, m, p);
     else
-        hipLaunchKernelGGL((k_mesh_elem<T, K, MODE, EPT, false>), dim3((unsigned)nb), dim3(p.block),
+        PG_LAUNCH((k_mesh_elem<T, K, MODE, EPT, false>), dim3((unsigned)nb), dim3(p.block),
                            0, s, m, p);
     return hipGetLastError();
 }
@@ -319,7 +319,7 @@ hipError_t launch_elem_dyn_t(const MeshView& m, const MeshPass& p, hipStream_t s
     const int64_t n_items = p.elist ? p.elist_n : m.n_elems;
     const int64_t nb = mesh_blocks(n_items, p.block, 1);
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_mesh_elem_dyn<T, MODE>), dim3((unsigned)nb), dim3(p.block), 0, s, m, p);
+    PG_LAUNCH((k_mesh_elem_dyn<T, MODE>), dim3((unsigned)nb), dim3(p.block), 0, s, m, p);
     return hipGetLastError();
 }
 
@@ -371,6 +371,11 @@ inline unsigned stream_grid(int64_t n, int per_block, int cap = 4096) {
 }
 
 }  // namespace
+
+LaunchEvents& armed_launch_events() {
+    thread_local LaunchEvents ev;
+    return ev;
+}
 
 int64_t mesh_blocks(int64_t n_items, int block, int ept) {
     const int64_t per = (int64_t)block * ept;

@@ -403,9 +403,9 @@ hipError_t launch_group_k(const GroupDev& g, int mode, hipStream_t s) {
     const dim3 grid((unsigned)group_blocks(g.n, BS)), block(BS);
     const dim3 grid_s((unsigned)group_blocks(g.n, BSS)), block_s(BSS);
     switch (mode) {
-        case G_FWD: hipLaunchKernelGGL((k_group<K, G_FWD, BS, NS>), grid, block, 0, s, g); break;
-        case G_REV: hipLaunchKernelGGL((k_group<K, G_REV, BSS, NS>), grid_s, block_s, 0, s, g); break;
-        default: hipLaunchKernelGGL((k_group<K, G_FWDREV, BSS, NS>), grid_s, block_s, 0, s, g); break;
+        case G_FWD: PG_LAUNCH((k_group<K, G_FWD, BS, NS>), grid, block, 0, s, g); break;
+        case G_REV: PG_LAUNCH((k_group<K, G_REV, BSS, NS>), grid_s, block_s, 0, s, g); break;
+        default: PG_LAUNCH((k_group<K, G_FWDREV, BSS, NS>), grid_s, block_s, 0, s, g); break;
     }
     return hipGetLastError();
 }

@@ -219,3 +219,18 @@ def test_broadcast_with_no_outputs(fusion):
     prog, (f, (g,)) = run_case(inputs.ProgramCase(spec, [x], "empty-bcast"), fusion=fusion)
     assert f.item() == 0.0
     assert torch.equal(g.cpu(), torch.zeros(3, dtype=torch.float64))
+
+
+@pytest.mark.parametrize("fusion", FUSION)
+def test_mesh_program_full_size(fusion, orc):
+    """The 128^3 element objective as constructs, in the benchmark's launch
+    configuration, against the mesh oracle (pinned to the program oracle at
+    small sizes)."""
+    m = inputs.hex_mesh(128)
+    case = inputs.program_mesh(m)
+    prog, (f, (g,)) = run_case(case, fusion=fusion)
+    f_ref, g_ref = orc.mesh_gradient(m.n_nodes, m.conn, m.B, m.w, m.x)
+    assert srel(f.item(), f_ref) < TOL_F64_F
+    assert rel(g.cpu().numpy(), g_ref) < TOL_F64_G
+    if fusion:
+        assert prog.info()["fwd_kernels"] == 2 and prog.info()["rev_kernels"] == 0
