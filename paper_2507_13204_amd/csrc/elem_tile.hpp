@@ -124,11 +124,11 @@ __device__ __forceinline__ void agg_clear(AggTable& t) {
     }
 }
 
-__device__ __forceinline__ void agg_add(AggTable& t, int32_t n, double c, double* g,
-                                        uint32_t shift) {
-    uint32_t h = agg_hash(n, shift);
+// Linear probing from slot h (probes already spent: `used`).
+__device__ __forceinline__ void agg_add_from(AggTable& t, int32_t n, double c, double* g,
+                                             uint32_t h, int used) {
 #pragma nounroll
-    for (int probe = 0; probe < kMaxProbe; ++probe) {
+    for (int probe = used; probe < kMaxProbe; ++probe) {
         const int32_t old = atomicCAS(&t.key[h], -1, n);
         if (old == -1 || old == n) {
             atomicAdd(&t.val[h], c);
@@ -137,6 +137,35 @@ __device__ __forceinline__ void agg_add(AggTable& t, int32_t n, double c, double
         h = (h + 1) & (kAggSlots - 1);
     }
     atomic_add_f64(g + n, c);
+}
+
+__device__ __forceinline__ void agg_add(AggTable& t, int32_t n, double c, double* g,
+                                        uint32_t shift) {
+    agg_add_from(t, n, c, g, agg_hash(n, shift), 0);
+}
+
+// The K contributions of one row: the first probes of all K are issued
+// before any result is examined, so their LDS round trips overlap instead of
+// queueing one behind the other; a contribution whose home slot holds
+// another node continues probing on its own.  (Two contributions of the row
+// to the same node: the second compare-and-swap finds the first's key.)
+template <int K>
+__device__ __forceinline__ void agg_add_row(AggTable& t, const int32_t (&n)[K], const double (&c)[K],
+                                            double* g, uint32_t shift) {
+    uint32_t h[K];
+    int32_t old[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        h[j] = agg_hash(n[j], shift);
+        old[j] = atomicCAS(&t.key[h[j]], -1, n[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (old[j] == -1 || old[j] == n[j])
+            atomicAdd(&t.val[h[j]], c[j]);
+        else
+            agg_add_from(t, n[j], c[j], g, (h[j] + 1) & (kAggSlots - 1), 1);
+    }
 }
 
 __device__ __forceinline__ void agg_flush(const AggTable& t, double* g) {
@@ -198,6 +227,9 @@ __device__ __forceinline__ double elem_tile(const TileArgs& a, int64_t first, in
             wv[i] = W[e[i]];
         }
     }
+    // The LDS table is cleared while the row loads are in flight (the
+    // previous tile's flush ended with a barrier).
+    if constexpr (is_atomic(MODE) && AGG) agg_clear(*tab);
     // Phase 2: the gather (or the stored forward value).
     if (a.u_in) {
 #pragma unroll
@@ -252,15 +284,18 @@ __device__ __forceinline__ double elem_tile(const TileArgs& a, int64_t first, in
             if (ok[i]) a.v_out[e[i]] = v[i];
     }
     if constexpr (is_atomic(MODE) && AGG) {
-        agg_clear(*tab);
-        __syncthreads();
+        __syncthreads();  // the table is clear
 #pragma unroll
         for (int i = 0; i < EPT; ++i)
             if (ok[i]) {
+                int32_t nn[K];
+                double cc[K];
 #pragma unroll
-                for (int j = 0; j < K; ++j)
-                    agg_add(*tab, (int32_t)(noff + c[i][j]), v[i] * to_f64(b[i][j]), a.gacc,
-                            a.hash_shift);
+                for (int j = 0; j < K; ++j) {
+                    nn[j] = (int32_t)(noff + c[i][j]);
+                    cc[j] = v[i] * to_f64(b[i][j]);
+                }
+                agg_add_row<K>(*tab, nn, cc, a.gacc, a.hash_shift);
             }
         __syncthreads();
         agg_flush(*tab, a.gacc);

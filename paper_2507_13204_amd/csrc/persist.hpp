@@ -105,9 +105,14 @@ k_atomic_persistent(Tiles tiles, TileArgs a, const double* fbar, int fbar_per_in
         const double fb = fbar ? fbar[fbar_per_inst ? dc.inst : 0] : 1.0;
         const double v = fb * wd * dpsi_from(u, s2);
         if (cur.ok) {
+            int32_t nn[K];
+            double cc[K];
 #pragma unroll
-            for (int j = 0; j < K; ++j)
-                agg_add(tab, (int32_t)(dc.noff + cur.c[j]), v * to_f64(cur.b[j]), a.gacc, dc.shift);
+            for (int j = 0; j < K; ++j) {
+                nn[j] = (int32_t)(dc.noff + cur.c[j]);
+                cc[j] = v * to_f64(cur.b[j]);
+            }
+            agg_add_row<K>(tab, nn, cc, a.gacc, dc.shift);
         }
         __syncthreads();
         for (int s = threadIdx.x; s < kAggSlots; s += blockDim.x) {

@@ -381,9 +381,10 @@ __global__ void __launch_bounds__(BS) k_group(GroupDev g) {
                 if (ok) {
                     const double ub = a.get(g.gather_slot);
                     if constexpr (K > 0) {
+                        double cc[K];
 #pragma unroll
-                        for (int j = 0; j < K; ++j)
-                            agg_add(tab, row.c[j], row.b[j] * ub, g.gsrc_shadow, g.hash_shift);
+                        for (int j = 0; j < K; ++j) cc[j] = row.b[j] * ub;
+                        agg_add_row<K>(tab, row.c, cc, g.gsrc_shadow, g.hash_shift);
                     } else {
                         for (int j = 0; j < g.gk; ++j)
                             agg_add(tab, g.gconn[i * g.gk + j], g.gB[i * g.gk + j] * ub,
