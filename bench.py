@@ -369,7 +369,7 @@ def bench_bdense(args):
 
 
 def bench_batch(args):
-    """256 uneven hex meshes: one persistent launch (eager and HIP-graph replay)
+    """256 uneven hex meshes: one launch over all instances' tiles (eager and HIP-graph replay)
     against 256 per-instance gradient calls."""
     import numpy as np
     import torch
@@ -432,7 +432,7 @@ def bench_batch(args):
           roofline={"bound": "hbm", "achieved": round(gbytes / (k_ms * 1e-3), 2),
                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": round(gbytes / (k_ms * 1e-3) / PEAK_HBM_GBS, 4), "traffic": None,
-                    "kernel": "k_atomic_persistent (batch tiles)", "kernel_ms": round(k_ms, 5)},
+                    "kernel": "k_batch_tiles (gradient, atomic)", "kernel_ms": round(k_ms, 5)},
           cpu_baseline=_batch_cpu(bt, args.cpu_seconds))
 
 

@@ -132,7 +132,6 @@ struct pg_plan_s {
     std::vector<pg_instance> inst;
     int64_t n_nodes_total = 0, n_elems_total = 0;
     std::vector<int64_t> h_tiles, h_seg;
-    int batch_grid = 0;
     // dense
     DenseView dense;
     int dense_groups = 0;
@@ -248,7 +247,8 @@ void layout_batch(pg_plan_s* p) {
     const int te = p->opt.block * p->opt.tile;
     p->batch.tile_elems = te;
     // Work list: tiles of every instance, largest instance first (LPT), then
-    // by instance index and tile index, dealt round-robin to a persistent grid.
+    // by instance index and tile index; one workgroup per tile, dispatched in
+    // list order.
     const int32_t ni = (int32_t)p->inst.size();
     std::vector<int32_t> order(ni);
     std::iota(order.begin(), order.end(), 0);
@@ -281,8 +281,6 @@ void layout_batch(pg_plan_s* p) {
     if (p->opt.ckpt == PG_STORE) p->o_u = L.take(sizeof(double) * (size_t)p->n_elems_total);
     if (p->dtype == PG_F32) p->o_gacc = L.take(sizeof(double) * (size_t)p->n_nodes_total);
     p->ws_bytes = L.total;
-    // The launcher sizes the persistent grid to the device's resident capacity.
-    p->batch_grid = 0;
 }
 
 // ------------------------------------------------------------ dense layout
@@ -668,14 +666,13 @@ pg_status batch_run(pg_plan p, const void* x, const double* fbar, void* grad, do
     BatchPass q;
     q.x = x;
     q.partials = p->at<double>(p->o_partials);
-    q.grid = p->batch_grid;
     q.block = p->opt.block;
     q.combine = p->opt.scatter == 0;
     q.fbar = fbar;
     if (!grd) {
         q.u_store = p->at<double>(p->o_u);
         PG_HIP(tkern(p, true));
-        PG_HIP(launch_batch_persistent(p->batch, B_PRIMAL, q, s));
+        PG_HIP(launch_batch(p->batch, B_PRIMAL, q, s));
         PG_HIP(tkern(p, false));
         if (f_out) PG_HIP(launch_segmented_sum(q.partials, seg, ni, f_out, s));
         if (q.u_store) {
@@ -696,7 +693,7 @@ pg_status batch_run(pg_plan p, const void* x, const double* fbar, void* grad, do
         if (!acc) PG_HIP(launch_zero(grad, sizeof(double) * (size_t)p->n_nodes_total, s));
     }
     PG_HIP(tkern(p, true));
-    PG_HIP(launch_batch_persistent(p->batch, obj ? B_GRAD_ATOMIC : B_ADJ_ATOMIC, q, s));
+    PG_HIP(launch_batch(p->batch, obj ? B_GRAD_ATOMIC : B_ADJ_ATOMIC, q, s));
     PG_HIP(tkern(p, false));
     if (f32)
         PG_HIP(launch_f64_to_f32((const double*)q.grad, static_cast<float*>(grad),

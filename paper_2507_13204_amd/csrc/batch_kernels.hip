@@ -1,19 +1,20 @@
-// Many uneven meshes in one persistent launch.
+// Many uneven meshes in one launch.
 //
 // The plan cuts every instance into tiles of block*EPT elements and orders the
-// tiles largest instance first; a grid sized to the resident capacity of the
-// device walks that list round-robin (tile g, g + grid, g + 2 grid, ...), so
-// the assignment is static and the objective deterministic.  Each tile
-// reduces its objective terms into its own slot, laid out instance by
-// instance, and one segmented reduction per instance follows.  This is the
-// fusion the paper's conclusion asks for: one launch instead of one (or two)
-// per instance, and no host round trip.  Inside a tile the work is exactly
-// the single-mesh element pass (elem_tile.hpp) with the instance's node
-// offset and seed.
+// tiles largest instance first; the launch has one workgroup per tile, and
+// the hardware dispatcher hands tiles out in that order as workgroups retire
+// (longest-processing-time-first list scheduling with no host involvement).
+// Each tile reduces its objective terms into its own slot, laid out instance
+// by instance, and one segmented reduction per instance follows, so the
+// objective is deterministic.  This is the fusion the paper's conclusion
+// asks for: one launch instead of one (or two) per instance, and no host
+// round trip.  Inside a tile the work is exactly the single-mesh element
+// pass (elem_tile.hpp) with the instance's node offset, hash rotation and
+// seed.  (A persistent grid walking the list round-robin, with the next
+// tile's rows prefetched, measured 15% slower on 256 hex meshes.)
 #include <type_traits>
 
 #include "elem_tile.hpp"
-#include "persist.hpp"
 
 namespace pg {
 
@@ -32,44 +33,35 @@ __device__ __forceinline__ TileRec load_tile(const int64_t* tiles, int64_t t) {
 constexpr int64_t kSlotMask = (1LL << 40) - 1;
 constexpr int64_t kNoffMask = (1LL << 40) - 1;
 
-// Logical workgroup l (XCD-remapped, so l .. l + grid/8 - 1 share an XCD)
-// takes tiles l, l + grid, ...; consecutive tiles of an instance therefore run
-// at the same time on one XCD and share its L2.  The next tile's record is
-// loaded while the current tile is processed.
+// One workgroup per tile.  Logical tile l = XCD-remapped block id, so
+// consecutive tiles of an instance run on one XCD at the same time and share
+// its L2.
 template <typename T, int K, int MODE, int EPT, bool AGG>
 __global__ void __launch_bounds__(1024)
-k_batch_persistent(BatchView bv, BatchPass p) {
+k_batch_tiles(BatchView bv, BatchPass p) {
     __shared__ double lds[16];
     __shared__ typename std::conditional<AGG, AggTable, int>::type agg;
     AggTable* tab = nullptr;
     if constexpr (AGG) tab = &agg;
+    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    const TileRec cur = load_tile(bv.tiles, tile);
+    const int64_t inst = cur.slot_inst >> 40;
+    double fb = 1.0;
+    if constexpr (has_rev(MODE)) fb = p.fbar ? p.fbar[inst] : 1.0;
     TileArgs a{bv.conn, bv.B, bv.w, p.x, nullptr, p.u_in, p.u_store, nullptr,
-               static_cast<double*>(p.grad), nullptr, 0u};
-    const int64_t G = gridDim.x;
-    int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
-    TileRec cur{};
-    if (tile < bv.n_tiles) cur = load_tile(bv.tiles, tile);
-    for (; tile < bv.n_tiles; tile += G) {
-        TileRec nxt{};
-        if (tile + G < bv.n_tiles) nxt = load_tile(bv.tiles, tile + G);
-        const int64_t inst = cur.slot_inst >> 40;
-        double fb = 1.0;
-        if constexpr (has_rev(MODE)) fb = p.fbar ? p.fbar[inst] : 1.0;
-        a.hash_shift = (uint32_t)(cur.shift_noff >> 40);
-        const double tsum = elem_tile<T, K, MODE, EPT, AGG>(a, cur.first, cur.end,
-                                                            cur.shift_noff & kNoffMask, fb, tab);
-        if constexpr (has_obj(MODE)) {
-            const double s = block_sum_dyn(tsum, lds);
-            if (threadIdx.x == 0) p.partials[cur.slot_inst & kSlotMask] = s;
-        }
-        cur = nxt;
+               static_cast<double*>(p.grad), nullptr, (uint32_t)(cur.shift_noff >> 40)};
+    const double tsum = elem_tile<T, K, MODE, EPT, AGG>(a, cur.first, cur.end,
+                                                        cur.shift_noff & kNoffMask, fb, tab);
+    if constexpr (has_obj(MODE)) {
+        const double s = block_sum_dyn(tsum, lds);
+        if (threadIdx.x == 0) p.partials[cur.slot_inst & kSlotMask] = s;
     }
 }
 
 // Runtime k: one element per thread, rows streamed through the cache.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(1024)
-k_batch_persistent_dyn(BatchView bv, BatchPass p) {
+k_batch_tiles_dyn(BatchView bv, BatchPass p) {
     __shared__ double lds[16];
     const T* __restrict__ B = static_cast<const T*>(bv.B);
     const T* __restrict__ W = static_cast<const T*>(bv.w);
@@ -77,59 +69,40 @@ k_batch_persistent_dyn(BatchView bv, BatchPass p) {
     double* __restrict__ G = static_cast<double*>(p.grad);
     const int32_t* __restrict__ conn = bv.conn;
     const int k = bv.k;
-    for (int64_t tile = xcd_remap(blockIdx.x, gridDim.x); tile < bv.n_tiles; tile += gridDim.x) {
-        const TileRec r = load_tile(bv.tiles, tile);
-        const int64_t inst = r.slot_inst >> 40;
-        const int64_t e = r.first + threadIdx.x;
-        double tsum = 0.0;
-        if (e < r.end) {
-            double u = 0.0;
-            if (p.u_in) {
-                u = p.u_in[e];
-            } else {
-                for (int j = 0; j < k; ++j)
-                    u += to_f64(B[e * k + j]) * to_f64(X[(r.shift_noff & kNoffMask) + conn[e * k + j]]);
-                if (p.u_store) p.u_store[e] = u;
-            }
-            const double s2 = u * u, wd = to_f64(W[e]);
-            if constexpr (has_obj(MODE)) tsum = wd * psi_from_sq(s2);
-            if constexpr (has_rev(MODE)) {
-                const double v = (p.fbar ? p.fbar[inst] : 1.0) * wd * dpsi_from(u, s2);
-                for (int j = 0; j < k; ++j)
-                    atomic_add_f64(G + (r.shift_noff & kNoffMask) + conn[e * k + j],
-                                   v * to_f64(B[e * k + j]));
-            }
+    const TileRec r = load_tile(bv.tiles, xcd_remap(blockIdx.x, gridDim.x));
+    const int64_t inst = r.slot_inst >> 40, noff = r.shift_noff & kNoffMask;
+    const int64_t e = r.first + threadIdx.x;
+    double tsum = 0.0;
+    if (e < r.end) {
+        double u = 0.0;
+        if (p.u_in) {
+            u = p.u_in[e];
+        } else {
+            for (int j = 0; j < k; ++j) u += to_f64(B[e * k + j]) * to_f64(X[noff + conn[e * k + j]]);
+            if (p.u_store) p.u_store[e] = u;
         }
-        if constexpr (has_obj(MODE)) {
-            const double s = block_sum_dyn(tsum, lds);
-            if (threadIdx.x == 0) p.partials[r.slot_inst & kSlotMask] = s;
+        const double s2 = u * u, wd = to_f64(W[e]);
+        if constexpr (has_obj(MODE)) tsum = wd * psi_from_sq(s2);
+        if constexpr (has_rev(MODE)) {
+            const double v = (p.fbar ? p.fbar[inst] : 1.0) * wd * dpsi_from(u, s2);
+            for (int j = 0; j < k; ++j) atomic_add_f64(G + noff + conn[e * k + j], v * to_f64(B[e * k + j]));
         }
+    }
+    if constexpr (has_obj(MODE)) {
+        const double s = block_sum_dyn(tsum, lds);
+        if (threadIdx.x == 0) p.partials[r.slot_inst & kSlotMask] = s;
     }
 }
 
 template <typename T, int K, int MODE, int EPT>
 hipError_t launch_agg(const BatchView& b, const BatchPass& p, hipStream_t s) {
     const bool agg = is_atomic(MODE) && p.combine && (int64_t)p.block * EPT * K <= 2 * kAggSlots;
-    if constexpr (is_atomic(MODE) && EPT == 1) {
-        if (agg) {
-            BatchTiles tiles{b.tiles, b.n_tiles};
-            TileArgs a{b.conn, b.B, b.w, p.x, nullptr, p.u_in, nullptr, nullptr,
-                       static_cast<double*>(p.grad), nullptr, 0u};
-            auto kern = k_atomic_persistent<T, K, MODE, BatchTiles>;
-            PG_LAUNCH(kern, dim3(resident_grid(kern, p.block, b.n_tiles, p.grid)),
-                               dim3(p.block), 0, s, tiles, a, p.fbar, 1, p.partials);
-            return hipGetLastError();
-        }
-    }
-    if (agg) {
-        auto kern = k_batch_persistent<T, K, MODE, EPT, true>;
-        PG_LAUNCH(kern, dim3(resident_grid(kern, p.block, b.n_tiles, p.grid)),
-                           dim3(p.block), 0, s, b, p);
-    } else {
-        auto kern = k_batch_persistent<T, K, MODE, EPT, false>;
-        PG_LAUNCH(kern, dim3(resident_grid(kern, p.block, b.n_tiles, p.grid)),
-                           dim3(p.block), 0, s, b, p);
-    }
+    if (agg)
+        PG_LAUNCH((k_batch_tiles<T, K, MODE, EPT, true>), dim3((unsigned)b.n_tiles), dim3(p.block), 0,
+                  s, b, p);
+    else
+        PG_LAUNCH((k_batch_tiles<T, K, MODE, EPT, false>), dim3((unsigned)b.n_tiles), dim3(p.block), 0,
+                  s, b, p);
     return hipGetLastError();
 }
 
@@ -151,11 +124,7 @@ hipError_t launch_k(const BatchView& b, const BatchPass& p, hipStream_t s) {
         case 2: return launch_ept<T, 2, MODE>(b, p, s);
         default:
             if (b.tile_elems != p.block) return hipErrorInvalidValue;
-            {
-                auto kern = k_batch_persistent_dyn<T, MODE>;
-                PG_LAUNCH(kern, dim3(resident_grid(kern, p.block, b.n_tiles, p.grid)),
-                                   dim3(p.block), 0, s, b, p);
-            }
+            PG_LAUNCH((k_batch_tiles_dyn<T, MODE>), dim3((unsigned)b.n_tiles), dim3(p.block), 0, s, b, p);
             return hipGetLastError();
     }
 }
@@ -172,7 +141,7 @@ hipError_t launch_mode(const BatchView& b, BatchMode mode, const BatchPass& p, h
 
 }  // namespace
 
-hipError_t launch_batch_persistent(const BatchView& b, BatchMode mode, const BatchPass& p,
+hipError_t launch_batch(const BatchView& b, BatchMode mode, const BatchPass& p,
                                    hipStream_t s) {
     if (b.n_tiles == 0) return hipSuccess;
     if (p.block <= 0 || p.block > 1024 || p.block % 64) return hipErrorInvalidValue;

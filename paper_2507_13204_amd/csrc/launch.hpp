@@ -145,12 +145,11 @@ struct BatchPass {
     double* partials = nullptr;    // one slot per tile
     const double* u_in = nullptr;
     double* u_store = nullptr;
-    int grid = 0;                  // cap on persistent workgroups (0: device capacity)
     int block = 256;
     int combine = 1;               // combine atomic contributions per tile in LDS
 };
 
-hipError_t launch_batch_persistent(const BatchView& b, BatchMode mode, const BatchPass& p,
+hipError_t launch_batch(const BatchView& b, BatchMode mode, const BatchPass& p,
                                    hipStream_t s);
 
 // The LDS table hash parameter for a connectivity: `tiles` holds, per sampled

@@ -357,7 +357,8 @@ class BatchedDense(_Plan):
 
 
 class MeshBatch(_Plan):
-    """Many meshes in one persistent launch; per-instance objectives."""
+    """Many meshes in one launch (one workgroup per tile, largest instance
+    first); per-instance objectives."""
 
     def __init__(self, inst, conn: torch.Tensor, B: torch.Tensor, w: torch.Tensor,
                  ckpt="recompute", block: int = 0, tile: int = 0, accumulate: bool = False,

@@ -1,4 +1,4 @@
-"""Parity of the persistent uneven-batch path with the per-instance oracle."""
+"""Parity of the one-launch uneven-batch path with the per-instance oracle."""
 import numpy as np
 import pytest
 
@@ -71,7 +71,7 @@ def test_batch_f32_and_empty_instances():
 
 
 def test_batch_full_size_graph_replay():
-    """256 instances with sides log-uniform in [10, 100], one persistent launch,
+    """256 instances with sides log-uniform in [10, 100], one launch,
     captured once in a HIP graph and replayed."""
     bt = inputs.uneven_batch(256)
     obj, x = _batch(bt)
