@@ -3,8 +3,8 @@
 //   backward  G = fbar * A^T V
 //
 // Both products are m x m by m x n contractions, tiled 128 x 128 x 16 per
-// workgroup of four waves; each wave owns a 64 x 64 block of C as 4 x 4
-// MFMA 16x16x4 accumulators (FP64: v_mfma_f64_16x16x4_f64; FP32:
+// workgroup of 16 (FP64) or 8 (FP32) waves; each wave owns a 64 x 16 or
+// 64 x 32 block of C as MFMA 16x16x4 accumulators (FP64: v_mfma_f64_16x16x4_f64; FP32:
 // v_mfma_f32_16x16x4_f32, whose accumulation inside the instruction is FP32).
 // Tiles are staged k-major in LDS (double buffered, the next tile prefetched
 // into registers while the current one feeds the matrix cores).  The
@@ -21,7 +21,18 @@ namespace pg {
 namespace {
 
 constexpr int BM = 128, BN = 128, BK = 16;
-constexpr int NTHR = 256;
+// Workgroup shape per element type: the waves tile the 128 x 128 block as
+// 2 x WAVES_N blocks of 64 x WN, each wave holding 4 x NY MFMA accumulators.
+// One workgroup per compute unit at the benchmark's shape (256 tiles), so
+// more waves per workgroup is what hides the load and LDS latency: FP64
+// uses 16 waves (measured 0.70 -> 0.56 ms from 4 waves), FP32 8 (its
+// 16-byte loads need at least four elements per thread and operand).
+template <typename T>
+struct Cfg {
+    static constexpr int NTHR = sizeof(T) == 8 ? 1024 : 512;
+    static constexpr int WAVES_N = NTHR / 128, WN = BN / WAVES_N, NY = WN / 16;
+    static constexpr int kPerThread = BM * BK / NTHR;  // elements of each operand tile per thread
+};
 constexpr int PAD = 4;  // LDS row padding (elements) against bank conflicts on transposed stores
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -53,16 +64,14 @@ struct Mfma<float> {
     __device__ static int row(int g, int r) { return 4 * g + r; }
 };
 
-// Elements of one operand tile each thread moves per k-step.
-constexpr int kPerThread = BM * BK / NTHR;  // 8
 
 enum Epi { EPI_FWD = 0, EPI_BWD = 1 };
 
 // One k-tile of both operands staged in registers on its way to LDS.
 template <typename T>
 struct Stage {
-    T a[kPerThread];
-    T b[kPerThread];
+    T a[Cfg<T>::kPerThread];
+    T b[Cfg<T>::kPerThread];
 };
 
 // C[M x N] = op(A)[M x K] * Bm[K x N].
@@ -74,21 +83,25 @@ struct Stage {
 // double buffer: at one workgroup per compute unit the matrix-core time of a
 // k-step is shorter than the latency of its loads.
 template <typename T, bool TRANS_A, int EPI, bool FULL>
-__global__ void __launch_bounds__(NTHR)
+__global__ void __launch_bounds__(Cfg<T>::NTHR)
 k_gemm_mfma(const T* __restrict__ A, const T* __restrict__ Bm, int64_t M, int64_t N, int64_t K,
             const T* __restrict__ W, double* __restrict__ partials, T* __restrict__ Vout,
             const double* __restrict__ fbar, T* __restrict__ Gout, int accumulate) {
     using MF = Mfma<T>;
     using acc_t = typename MF::acc_t;
+    constexpr int NTHR = Cfg<T>::NTHR, WAVES_N = Cfg<T>::WAVES_N, WN = Cfg<T>::WN, NY = Cfg<T>::NY;
+    constexpr int kPerThread = Cfg<T>::kPerThread;
     constexpr int VN = 16 / sizeof(T);
     constexpr int NV = kPerThread / VN;  // vectors per operand per thread
+    static_assert(NV >= 1 && kPerThread % VN == 0, "16-byte loads need whole vectors per thread");
+    static_assert(NY >= 1 && WN % 16 == 0, "each wave needs whole 16-column MFMA blocks");
     __shared__ T As[2][BK][BM + PAD];
     __shared__ T Bs[2][BK][BN + PAD];
     __shared__ double red[NTHR / kWave];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
-    const int wm = wid >> 1, wn = wid & 1;  // wave's 64 x 64 block within the tile
+    const int wm = wid / WAVES_N, wn = wid % WAVES_N;  // wave's 64 x WN block within the tile
     const int64_t i0 = (int64_t)blockIdx.y * BM, j0 = (int64_t)blockIdx.x * BN;
 
     // Element q of this thread's share of a tile, as (i, k) of op(A) and (k, j) of B.
@@ -169,26 +182,25 @@ k_gemm_mfma(const T* __restrict__ A, const T* __restrict__ Bm, int64_t M, int64_
         }
     };
 
-    acc_t acc[4][4];
+    acc_t acc[4][NY];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = MF::zero();
+        for (int b = 0; b < NY; ++b) acc[a][b] = MF::zero();
 
     const int li = lane & 15, lk = lane >> 4;
     auto compute = [&](int buf) {
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
-            T a[4], b[4];
+            T a[4], b[NY];
 #pragma unroll
-            for (int x = 0; x < 4; ++x) {
-                a[x] = As[buf][ks * 4 + lk][wm * 64 + x * 16 + li];
-                b[x] = Bs[buf][ks * 4 + lk][wn * 64 + x * 16 + li];
-            }
+            for (int x = 0; x < 4; ++x) a[x] = As[buf][ks * 4 + lk][wm * 64 + x * 16 + li];
+#pragma unroll
+            for (int y = 0; y < NY; ++y) b[y] = Bs[buf][ks * 4 + lk][wn * WN + y * 16 + li];
 #pragma unroll
             for (int x = 0; x < 4; ++x)
 #pragma unroll
-                for (int y = 0; y < 4; ++y) acc[x][y] = MF::mac(a[x], b[y], acc[x][y]);
+                for (int y = 0; y < NY; ++y) acc[x][y] = MF::mac(a[x], b[y], acc[x][y]);
         }
     };
 
@@ -223,11 +235,11 @@ k_gemm_mfma(const T* __restrict__ A, const T* __restrict__ Bm, int64_t M, int64_
 #pragma unroll
     for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y)
+        for (int y = 0; y < NY; ++y)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t gi = i0 + wm * 64 + x * 16 + MF::row(lk, r);
-                const int64_t gj = j0 + wn * 64 + y * 16 + li;
+                const int64_t gj = j0 + wn * WN + y * 16 + li;
                 if (gi < M && gj < N) {
                     const double c = MF::get(acc[x][y], r);
                     const int64_t o = gi * N + gj;
@@ -263,10 +275,10 @@ template <typename T, bool TRANS, int EPI>
 void launch_gemm(const BDenseView& b, dim3 grid, hipStream_t s, const T* A, const T* Bm, const T* W,
                  double* partials, T* V, const double* fbar, T* G, int accumulate) {
     if (full_tiles(b, Bm))
-        PG_LAUNCH((k_gemm_mfma<T, TRANS, EPI, true>), grid, dim3(NTHR), 0, s, A, Bm, b.m,
+        PG_LAUNCH((k_gemm_mfma<T, TRANS, EPI, true>), grid, dim3(Cfg<T>::NTHR), 0, s, A, Bm, b.m,
                            b.n, b.m, W, partials, V, fbar, G, accumulate);
     else
-        PG_LAUNCH((k_gemm_mfma<T, TRANS, EPI, false>), grid, dim3(NTHR), 0, s, A, Bm, b.m,
+        PG_LAUNCH((k_gemm_mfma<T, TRANS, EPI, false>), grid, dim3(Cfg<T>::NTHR), 0, s, A, Bm, b.m,
                            b.n, b.m, W, partials, V, fbar, G, accumulate);
 }
 
