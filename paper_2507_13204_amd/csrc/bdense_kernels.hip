@@ -91,7 +91,9 @@ k_gemm_mfma(const T* __restrict__ A, const T* __restrict__ Bm, int64_t M, int64_
     using acc_t = typename MF::acc_t;
     constexpr int NTHR = Cfg<T>::NTHR, WAVES_N = Cfg<T>::WAVES_N, WN = Cfg<T>::WN, NY = Cfg<T>::NY;
     constexpr int kPerThread = Cfg<T>::kPerThread;
-    constexpr int VN = 16 / sizeof(T);
+    // Vector width of the operand loads: 16 bytes, or fewer elements when a
+    // thread moves fewer per tile.
+    constexpr int VN = (int)(16 / sizeof(T)) < kPerThread ? (int)(16 / sizeof(T)) : kPerThread;
     constexpr int NV = kPerThread / VN;  // vectors per operand per thread
     static_assert(NV >= 1 && kPerThread % VN == 0, "16-byte loads need whole vectors per thread");
     static_assert(NY >= 1 && WN % 16 == 0, "each wave needs whole 16-column MFMA blocks");
@@ -139,7 +141,7 @@ k_gemm_mfma(const T* __restrict__ A, const T* __restrict__ Bm, int64_t M, int64_
     };
     auto gload = [&](Stage<T>& st, int64_t k0) {
         if constexpr (FULL) {
-            using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+            typedef T V __attribute__((ext_vector_type(VN)));
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 int ii, kk, bk, bj;
@@ -148,12 +150,10 @@ k_gemm_mfma(const T* __restrict__ A, const T* __restrict__ Bm, int64_t M, int64_
                 const T* pa = TRANS_A ? A + (k0 + kk) * K + (i0 + ii) : A + (i0 + ii) * K + (k0 + kk);
                 const V va = *reinterpret_cast<const V*>(pa);
                 const V vb = *reinterpret_cast<const V*>(Bm + (k0 + bk) * N + (j0 + bj));
-                const T* ea = reinterpret_cast<const T*>(&va);
-                const T* eb = reinterpret_cast<const T*>(&vb);
 #pragma unroll
                 for (int c = 0; c < VN; ++c) {
-                    st.a[v * VN + c] = ea[c];
-                    st.b[v * VN + c] = eb[c];
+                    st.a[v * VN + c] = va[c];
+                    st.b[v * VN + c] = vb[c];
                 }
             }
         } else {
