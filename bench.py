@@ -214,6 +214,30 @@ def bench_hex(args):
     out["hvp_ms"] = round(_timed(lambda: obj0.hvp(x0, dvec, out=hv), 20, 3), 5)
     out["jvp_ms"] = round(_timed(lambda: obj0.jvp(x0, dvec), 20, 3), 5)
 
+    # the autograd form: forward = objective, backward = adjoint seeded with
+    # grad_output, for recompute and store checkpointing (host autograd
+    # overhead included, as a user of the Function sees it)
+    from paper_2507_13204_amd import MeshFn
+    ag = {}
+    for ck in ("recompute", "store"):
+        oa = MeshObjective(conn, B, w, m.n_nodes, ckpt=ck)
+        xa = x.detach().clone().requires_grad_(True)
+
+        def fwd():
+            with torch.no_grad():
+                MeshFn.apply(xa, oa)
+
+        def fwd_bwd():
+            xa.grad = None
+            MeshFn.apply(xa, oa).backward()
+
+        t_f = _timed(fwd, 20, 3)
+        t_fb = _timed(fwd_bwd, 20, 3)
+        ag[ck] = {"forward_ms": round(t_f, 5), "forward_backward_ms": round(t_fb, 5),
+                  "fwd_plus_bwd_over_fwd": round(t_fb / t_f, 4), "cache": "warm"}
+        oa.close()
+    out["autograd"] = ag
+
     if not args.no_variants:
         variants = {}
         for adj in ("atomic", "gather", "colour"):
