@@ -233,11 +233,11 @@ struct ProgTaps {
     double coef[kMaxTaps] = {};
 };
 
-// One non-pointwise construct (stencil, gather, scan, segment sum,
-// broadcast) as its kernels see it.  Forward: y = op(a) over n outputs.
-// Reverse: ab receives the adjoint of the output shadow yb, stored
-// (accumulate 0) or added (accumulate 1); the gather's reverse is always an
-// atomic addition.  The scan uses scratch (prog_scan_chunks(n) doubles) for
+// One stand-alone non-pointwise construct (stencil, scan, segment sum,
+// broadcast; gathers run as group kernels) as its kernels see it.
+// Forward: y = op(a) over n outputs.  Reverse: ab receives the adjoint of
+// the output shadow yb, stored (accumulate 0) or added (accumulate 1).
+// The scan uses scratch (prog_scan_chunks(n) doubles) for
 // its chunk totals.  Segment sum and broadcast take segment offsets offs
 // (n_seg + 1 entries): the sum has n = n_seg outputs, the broadcast n =
 // offs[n_seg].
@@ -247,9 +247,6 @@ struct ProgOpDev {
     const double* a = nullptr;
     double* y = nullptr;
     ProgTaps taps;
-    int32_t k = 0;
-    const int32_t* conn = nullptr;
-    const double* B = nullptr;
     const double* yb = nullptr;
     double* ab = nullptr;
     int accumulate = 1;

@@ -755,9 +755,6 @@ pg_status pg_prog_run(pg_prog p, const double* const* inputs, double* f_out, dou
         d.a = val[(size_t)op.a];
         d.y = at(p, op.val_off);
         d.taps = op.taps;
-        d.k = op.k;
-        d.conn = op.conn;
-        d.B = op.B;
         d.yb = shd[(size_t)v];
         d.ab = ops[(size_t)op.a].active ? shd[(size_t)op.a] : nullptr;
         d.accumulate = p->op_acc[(size_t)v] != D_STORE;
