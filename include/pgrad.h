@@ -96,9 +96,13 @@ typedef struct {
                            (the shadow-argument convention of the generated
                            gradient in section 4) */
     int32_t scatter;    /* atomic adjoint only: 0 = default (combine each
-                           workgroup's contributions per node in LDS, then one
-                           global atomic per node), 1 = one global atomic per
-                           contribution */
+                           workgroup's contributions per node in an LDS hash
+                           table, then one global atomic per node; a single
+                           mesh's plan picks a 2048- or 4096-slot table by
+                           simulating it on sampled workgroups), 1 = one
+                           global atomic per contribution, 2 = combine in a
+                           4096-slot table, 3 = combine in a 2048-slot table
+                           (2 and 3: single meshes; batches treat them as 0) */
 } pg_options;
 
 /* One instance of a mesh batch: its nodes are x[node_off .. node_off+n_nodes)

@@ -80,38 +80,68 @@ namespace pg {
 static const uint32_t kShiftCandidates[] = {2533, 1237, 3371, 615, 1861, 2967, 347, 3779, 1493, 2207,
                                             3061, 881};
 
-uint32_t choose_hash_shift(const int32_t* const* tiles, const int64_t* counts, int64_t n_tiles) {
-    constexpr int kSlots = 4096, kProbe = 64;
-    std::vector<int32_t> key(kSlots);
+// Probe count of an S-slot table with rotation `shift` on the sampled tiles
+// (an insert that finds no slot within kProbe steps counts 4 * kProbe: it
+// goes to a global atomic); stops early past `stop_at`.
+int64_t table_cost(const int32_t* const* tiles, const int64_t* counts, int64_t n_tiles, int slots,
+                   uint32_t shift, int64_t stop_at) {
+    constexpr int kProbe = 64;
+    std::vector<int32_t> key((size_t)slots);
+    const uint32_t mask = (uint32_t)slots - 1;
+    int64_t cost = 0;
+    for (int64_t t = 0; t < n_tiles && cost < stop_at; ++t) {
+        std::fill(key.begin(), key.end(), -1);
+        for (int64_t q = 0; q < counts[t]; ++q) {
+            const int32_t n = tiles[t][q];
+            const uint32_t u = (uint32_t)n;
+            uint32_t h = (u + (u >> 12) * shift) & mask;
+            int probe = 0;
+            while (probe < kProbe && key[h] != -1 && key[h] != n) {
+                h = (h + 1) & mask;
+                ++probe;
+            }
+            if (probe == kProbe) {
+                cost += 4 * kProbe;
+            } else {
+                key[h] = n;
+                cost += probe;
+            }
+        }
+    }
+    return cost;
+}
+
+uint32_t choose_hash_shift(const int32_t* const* tiles, const int64_t* counts, int64_t n_tiles,
+                           int slots, int64_t* cost_out) {
     uint32_t best = kShiftCandidates[0];
     int64_t best_cost = INT64_MAX;
     for (uint32_t cand : kShiftCandidates) {
-        int64_t cost = 0;
-        for (int64_t t = 0; t < n_tiles && cost < best_cost; ++t) {
-            std::fill(key.begin(), key.end(), -1);
-            for (int64_t q = 0; q < counts[t]; ++q) {
-                const int32_t n = tiles[t][q];
-                const uint32_t u = (uint32_t)n;
-                uint32_t h = (u + (u >> 12) * cand) & (kSlots - 1);
-                int probe = 0;
-                while (probe < kProbe && key[h] != -1 && key[h] != n) {
-                    h = (h + 1) & (kSlots - 1);
-                    ++probe;
-                }
-                if (probe == kProbe) {
-                    cost += 4 * kProbe;  // spills to a global atomic
-                } else {
-                    key[h] = n;
-                    cost += probe;
-                }
-            }
-        }
+        const int64_t cost = table_cost(tiles, counts, n_tiles, slots, cand, best_cost);
         if (cost < best_cost) {
             best_cost = cost;
             best = cand;
         }
     }
+    if (cost_out) *cost_out = best_cost;
     return best;
+}
+
+void choose_table(const int32_t* const* tiles, const int64_t* counts, int64_t n_tiles, int* slots,
+                  uint32_t* shift) {
+    int64_t c_big = 0, c_small = 0;
+    const uint32_t s_big = choose_hash_shift(tiles, counts, n_tiles, 4096, &c_big);
+    const uint32_t s_small = choose_hash_shift(tiles, counts, n_tiles, 2048, &c_small);
+    // A workgroup clears and flushes every slot of its table: the smaller
+    // table saves 2048 slot visits per workgroup, worth it while its extra
+    // probes stay below a quarter of that.
+    const int64_t saved = n_tiles * 2048 / 4;
+    if (n_tiles > 0 && c_small - c_big < saved) {
+        *slots = 2048;
+        *shift = s_small;
+    } else {
+        *slots = 4096;
+        *shift = s_big;
+    }
 }
 
 }  // namespace pg
@@ -124,6 +154,7 @@ struct pg_plan_s {
     MeshView mesh;
     int64_t mesh_blocks_n = 0;
     uint32_t hash_shift = 2533;  // LDS table hash parameter chosen at bind time
+    int agg_slots = 4096;        // LDS table size chosen at bind time
     // colour classes: elements of colour c are elist[colour_off[c] .. colour_off[c+1])
     std::vector<int64_t> colour_off;
     size_t o_elist = NONE;
@@ -187,8 +218,8 @@ pg_status check_opts(const pg_options* o, pg_options* out) {
         return fail(PG_EINVAL, "options.tile %d must be 1, 2 or 4", out->tile);
     if (out->accumulate != 0 && out->accumulate != 1)
         return fail(PG_EINVAL, "options.accumulate must be 0 or 1");
-    if (out->scatter != 0 && out->scatter != 1)
-        return fail(PG_EINVAL, "options.scatter must be 0 or 1");
+    if (out->scatter < 0 || out->scatter > 3)
+        return fail(PG_EINVAL, "options.scatter must be 0, 1, 2 or 3");
     return PG_OK;
 }
 
@@ -401,8 +432,9 @@ MeshPass base_pass(pg_plan p, const void* x) {
     q.partials = p->at<double>(p->o_partials);
     q.block = p->opt.block;
     q.ept = p->opt.tile;
-    q.combine = p->opt.scatter == 0;
+    q.combine = p->opt.scatter != 1;
     q.hash_shift = p->hash_shift;
+    q.agg_slots = p->agg_slots;
     return q;
 }
 
@@ -523,7 +555,17 @@ uint32_t shift_of(const std::vector<std::vector<int32_t>>& tiles) {
         ptr.push_back(t.data());
         cnt.push_back((int64_t)t.size());
     }
-    return choose_hash_shift(ptr.data(), cnt.data(), (int64_t)tiles.size());
+    return choose_hash_shift(ptr.data(), cnt.data(), (int64_t)tiles.size(), 4096, nullptr);
+}
+
+void table_of(const std::vector<std::vector<int32_t>>& tiles, int* slots, uint32_t* shift) {
+    std::vector<const int32_t*> ptr;
+    std::vector<int64_t> cnt;
+    for (const auto& t : tiles) {
+        ptr.push_back(t.data());
+        cnt.push_back((int64_t)t.size());
+    }
+    choose_table(ptr.data(), cnt.data(), (int64_t)tiles.size(), slots, shift);
 }
 
 // Greedy colouring in element order (plan time, on the host): element e
@@ -584,12 +626,23 @@ pg_status mesh_bind(pg_plan p, hipStream_t s) {
     PG_HIP(hipMemcpyAsync(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
     if (hflag) return fail(PG_ERANGE, "connectivity has an entry outside [0, %lld)", (long long)m.n_nodes);
-    if (p->opt.scatter == 0 && m.n_elems > 0) {
+    if (p->opt.scatter != 1 && m.n_elems > 0) {
         std::vector<std::vector<int32_t>> tiles;
         pg_status hst = sample_mesh_tiles(m.conn, m.n_elems, m.k, 0,
                                           (int64_t)p->opt.block * p->opt.tile, 24, tiles, s);
         if (hst != PG_OK) return hst;
-        p->hash_shift = shift_of(tiles);
+        table_of(tiles, &p->agg_slots, &p->hash_shift);
+        if (p->opt.scatter >= 2) {  // the caller fixed the table size
+            p->agg_slots = p->opt.scatter == 2 ? 4096 : 2048;
+            std::vector<const int32_t*> ptr;
+            std::vector<int64_t> cnt;
+            for (const auto& t : tiles) {
+                ptr.push_back(t.data());
+                cnt.push_back((int64_t)t.size());
+            }
+            p->hash_shift = choose_hash_shift(ptr.data(), cnt.data(), (int64_t)tiles.size(),
+                                              p->agg_slots, nullptr);
+        }
     }
     if (p->opt.adjoint == PG_ADJ_COLOUR) {
         pg_status cst = mesh_colour(p, s);
@@ -619,7 +672,7 @@ pg_status batch_bind(pg_plan p, hipStream_t s) {
     }
     // LDS table hash parameter per instance, written into its tile records.
     const int64_t nt = p->batch.n_tiles, ni = (int64_t)p->inst.size();
-    if (p->opt.scatter == 0) {
+    if (p->opt.scatter != 1) {
         std::vector<uint32_t> shift((size_t)ni, 2533u);
         for (int64_t i = 0; i < ni; ++i) {
             const pg_instance& in = p->inst[(size_t)i];
@@ -667,7 +720,7 @@ pg_status batch_run(pg_plan p, const void* x, const double* fbar, void* grad, do
     q.x = x;
     q.partials = p->at<double>(p->o_partials);
     q.block = p->opt.block;
-    q.combine = p->opt.scatter == 0;
+    q.combine = p->opt.scatter != 1;
     q.fbar = fbar;
     if (!grd) {
         q.u_store = p->at<double>(p->o_u);

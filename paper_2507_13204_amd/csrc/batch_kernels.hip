@@ -36,13 +36,13 @@ constexpr int64_t kNoffMask = (1LL << 40) - 1;
 // One workgroup per tile.  Logical tile l = XCD-remapped block id, so
 // consecutive tiles of an instance run on one XCD at the same time and share
 // its L2.
-template <typename T, int K, int MODE, int EPT, bool AGG>
+template <typename T, int K, int MODE, int EPT, int AGG>
 __global__ void __launch_bounds__(1024)
 k_batch_tiles(BatchView bv, BatchPass p) {
     __shared__ double lds[16];
-    __shared__ typename std::conditional<AGG, AggTable, int>::type agg;
-    AggTable* tab = nullptr;
-    if constexpr (AGG) tab = &agg;
+    __shared__ AggOf<AGG> agg;
+    AggOf<AGG>* tab = nullptr;
+    if constexpr (AGG > 0) tab = &agg;
     const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
     const TileRec cur = load_tile(bv.tiles, tile);
     const int64_t inst = cur.slot_inst >> 40;
@@ -98,10 +98,10 @@ template <typename T, int K, int MODE, int EPT>
 hipError_t launch_agg(const BatchView& b, const BatchPass& p, hipStream_t s) {
     const bool agg = is_atomic(MODE) && p.combine && (int64_t)p.block * EPT * K <= 2 * kAggSlots;
     if (agg)
-        PG_LAUNCH((k_batch_tiles<T, K, MODE, EPT, true>), dim3((unsigned)b.n_tiles), dim3(p.block), 0,
+        PG_LAUNCH((k_batch_tiles<T, K, MODE, EPT, kAggSlots>), dim3((unsigned)b.n_tiles), dim3(p.block), 0,
                   s, b, p);
     else
-        PG_LAUNCH((k_batch_tiles<T, K, MODE, EPT, false>), dim3((unsigned)b.n_tiles), dim3(p.block), 0,
+        PG_LAUNCH((k_batch_tiles<T, K, MODE, EPT, 0>), dim3((unsigned)b.n_tiles), dim3(p.block), 0,
                   s, b, p);
     return hipGetLastError();
 }

@@ -99,33 +99,41 @@ __device__ __forceinline__ void load_b_row(const float* __restrict__ B, int64_t 
 // node numbers in consecutive slots, so the flush touches few cache lines
 // per instruction; a contribution that finds no slot within kMaxProbe steps
 // goes straight to global memory, so any connectivity is handled.
-constexpr int kAggSlots = 4096;
+constexpr int kAggSlots = 4096;       // the default table
+constexpr int kAggSlotsSmall = 2048;  // chosen by the plan when its workgroups touch few nodes
 constexpr int kMaxProbe = 64;
 
-struct AggTable {
-    int32_t key[kAggSlots];
-    double val[kAggSlots];
+template <int S>
+struct AggTableT {
+    static constexpr int kSlots = S;
+    int32_t key[S];
+    double val[S];
 };
+using AggTable = AggTableT<kAggSlots>;
 
 // Consecutive node numbers go to consecutive slots (so the flush touches few
 // cache lines per instruction); each further window of 4096 node numbers is
 // rotated by `shift` slots, so ranges that are a plane (or an instance) apart
-// in the numbering land on different slots.  The plan picks `shift` for its
-// connectivity by simulating the table on sampled workgroups.
+// in the numbering land on different slots.  The plan picks `shift` (and the
+// table size) for its connectivity by simulating the table on sampled
+// workgroups.
+template <int S>
 __device__ __forceinline__ uint32_t agg_hash(int32_t n, uint32_t shift) {
     const uint32_t u = (uint32_t)n;
-    return (u + (u >> 12) * shift) & (kAggSlots - 1);
+    return (u + (u >> 12) * shift) & (S - 1);
 }
 
-__device__ __forceinline__ void agg_clear(AggTable& t) {
-    for (int s = threadIdx.x; s < kAggSlots; s += blockDim.x) {
+template <int S>
+__device__ __forceinline__ void agg_clear(AggTableT<S>& t) {
+    for (int s = threadIdx.x; s < S; s += blockDim.x) {
         t.key[s] = -1;
         t.val[s] = 0.0;
     }
 }
 
 // Linear probing from slot h (probes already spent: `used`).
-__device__ __forceinline__ void agg_add_from(AggTable& t, int32_t n, double c, double* g,
+template <int S>
+__device__ __forceinline__ void agg_add_from(AggTableT<S>& t, int32_t n, double c, double* g,
                                              uint32_t h, int used) {
 #pragma nounroll
     for (int probe = used; probe < kMaxProbe; ++probe) {
@@ -134,14 +142,15 @@ __device__ __forceinline__ void agg_add_from(AggTable& t, int32_t n, double c, d
             atomicAdd(&t.val[h], c);
             return;
         }
-        h = (h + 1) & (kAggSlots - 1);
+        h = (h + 1) & (S - 1);
     }
     atomic_add_f64(g + n, c);
 }
 
-__device__ __forceinline__ void agg_add(AggTable& t, int32_t n, double c, double* g,
+template <int S>
+__device__ __forceinline__ void agg_add(AggTableT<S>& t, int32_t n, double c, double* g,
                                         uint32_t shift) {
-    agg_add_from(t, n, c, g, agg_hash(n, shift), 0);
+    agg_add_from(t, n, c, g, agg_hash<S>(n, shift), 0);
 }
 
 // The K contributions of one row: the first probes of all K are issued
@@ -149,14 +158,14 @@ __device__ __forceinline__ void agg_add(AggTable& t, int32_t n, double c, double
 // queueing one behind the other; a contribution whose home slot holds
 // another node continues probing on its own.  (Two contributions of the row
 // to the same node: the second compare-and-swap finds the first's key.)
-template <int K>
-__device__ __forceinline__ void agg_add_row(AggTable& t, const int32_t (&n)[K], const double (&c)[K],
-                                            double* g, uint32_t shift) {
+template <int K, int S>
+__device__ __forceinline__ void agg_add_row(AggTableT<S>& t, const int32_t (&n)[K],
+                                            const double (&c)[K], double* g, uint32_t shift) {
     uint32_t h[K];
     int32_t old[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        h[j] = agg_hash(n[j], shift);
+        h[j] = agg_hash<S>(n[j], shift);
         old[j] = atomicCAS(&t.key[h[j]], -1, n[j]);
     }
 #pragma unroll
@@ -164,17 +173,21 @@ __device__ __forceinline__ void agg_add_row(AggTable& t, const int32_t (&n)[K], 
         if (old[j] == -1 || old[j] == n[j])
             atomicAdd(&t.val[h[j]], c[j]);
         else
-            agg_add_from(t, n[j], c[j], g, (h[j] + 1) & (kAggSlots - 1), 1);
+            agg_add_from(t, n[j], c[j], g, (h[j] + 1) & (S - 1), 1);
     }
 }
 
-__device__ __forceinline__ void agg_flush(const AggTable& t, double* g) {
-    for (int s = threadIdx.x; s < kAggSlots; s += blockDim.x) {
+template <int S>
+__device__ __forceinline__ void agg_flush(const AggTableT<S>& t, double* g) {
+    for (int s = threadIdx.x; s < S; s += blockDim.x) {
         const int32_t n = t.key[s];
         if (n >= 0) atomic_add_f64(g + n, t.val[s]);
     }
 }
 
+// LDS table type of a kernel combining with S slots (S = 0: no table).
+template <int S>
+using AggOf = typename std::conditional<(S > 0), AggTableT<(S > 0 ? S : 64)>, int>::type;
 
 // Arguments of one element tile (device pointers; element-indexed arrays are
 // indexed by the element number e, node arrays by noff + conn[e, j]).
@@ -194,12 +207,13 @@ struct TileArgs {
 
 // The element work of one workgroup: items first + i*blockDim + tid (i < EPT)
 // below `end`.  Loads for all owned elements are issued before any
-// arithmetic; with AGG the atomic scatter is combined in `tab` (every thread
+// arithmetic; with AGG > 0 the atomic scatter is combined in `tab`, an
+// AGG-slot LDS table (every thread
 // of the workgroup must call this).  Returns this thread's sum of the
 // objective terms w_e psi(u_e) (0 when the mode has no objective).
-template <typename T, int K, int MODE, int EPT, bool AGG>
+template <typename T, int K, int MODE, int EPT, int AGG>
 __device__ __forceinline__ double elem_tile(const TileArgs& a, int64_t first, int64_t end,
-                                            int64_t noff, double fb, AggTable* tab) {
+                                            int64_t noff, double fb, AggOf<AGG>* tab) {
     const T* __restrict__ B = static_cast<const T*>(a.B);
     const T* __restrict__ W = static_cast<const T*>(a.w);
     const T* __restrict__ X = static_cast<const T*>(a.x) + noff;
@@ -229,7 +243,7 @@ __device__ __forceinline__ double elem_tile(const TileArgs& a, int64_t first, in
     }
     // The LDS table is cleared while the row loads are in flight (the
     // previous tile's flush ended with a barrier).
-    if constexpr (is_atomic(MODE) && AGG) agg_clear(*tab);
+    if constexpr (is_atomic(MODE) && AGG > 0) agg_clear(*tab);
     // Phase 2: the gather (or the stored forward value).
     if (a.u_in) {
 #pragma unroll
@@ -283,7 +297,7 @@ __device__ __forceinline__ double elem_tile(const TileArgs& a, int64_t first, in
         for (int i = 0; i < EPT; ++i)
             if (ok[i]) a.v_out[e[i]] = v[i];
     }
-    if constexpr (is_atomic(MODE) && AGG) {
+    if constexpr (is_atomic(MODE) && AGG > 0) {
         __syncthreads();  // the table is clear
 #pragma unroll
         for (int i = 0; i < EPT; ++i)
@@ -295,7 +309,7 @@ __device__ __forceinline__ double elem_tile(const TileArgs& a, int64_t first, in
                     nn[j] = (int32_t)(noff + c[i][j]);
                     cc[j] = v[i] * to_f64(b[i][j]);
                 }
-                agg_add_row<K>(*tab, nn, cc, a.gacc, a.hash_shift);
+                agg_add_row<K, AGG>(*tab, nn, cc, a.gacc, a.hash_shift);
             }
         __syncthreads();
         agg_flush(*tab, a.gacc);

@@ -76,6 +76,7 @@ struct MeshPass {
     int ept = 1;
     int combine = 1;               // combine atomic contributions in LDS first
     uint32_t hash_shift = 2533;    // LDS table hash parameter (see choose_hash_shift)
+    int agg_slots = 4096;          // LDS table size: 4096 or 2048 (see choose_hash_shift)
 };
 
 // Number of workgroups an element pass over n items launches.
@@ -155,7 +156,13 @@ hipError_t launch_batch(const BatchView& b, BatchMode mode, const BatchPass& p,
 // The LDS table hash parameter for a connectivity: `tiles` holds, per sampled
 // workgroup tile, the node numbers its elements touch (in element order);
 // returns the candidate shift with the fewest simulated probe steps.
-uint32_t choose_hash_shift(const int32_t* const* tiles, const int64_t* counts, int64_t n_tiles);
+// LDS table choices from sampled workgroup tiles (node numbers each touches):
+// the best hash rotation for an S-slot table (its simulated probe count in
+// *cost_out when not null), and, for single meshes, the table size too.
+uint32_t choose_hash_shift(const int32_t* const* tiles, const int64_t* counts, int64_t n_tiles,
+                           int slots, int64_t* cost_out);
+void choose_table(const int32_t* const* tiles, const int64_t* counts, int64_t n_tiles, int* slots,
+                  uint32_t* shift);
 
 // ------------------------------------------------------------------ dense
 

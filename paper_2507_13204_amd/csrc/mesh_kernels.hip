@@ -23,19 +23,19 @@ namespace pg {
 namespace {
 
 // Compile-time K: every row lives in registers.
-template <typename T, int K, int MODE, int EPT, bool AGG>
+template <typename T, int K, int MODE, int EPT, int AGG>
 __global__ void __launch_bounds__(1024)
 k_mesh_elem(MeshView m, MeshPass p) {
     __shared__ double lds[16];
-    __shared__ typename std::conditional<AGG, AggTable, int>::type agg;
+    __shared__ AggOf<AGG> agg;
     const int64_t n_items = p.elist ? p.elist_n : m.n_elems;
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
     double fb = 1.0;
     if constexpr (has_rev(MODE)) fb = p.fbar ? p.fbar[0] : 1.0;
     TileArgs a{m.conn, m.B, m.w, p.x, p.xd, p.u_in, p.u_store, p.v_out, p.gacc, p.elist,
                p.hash_shift};
-    AggTable* tab = nullptr;
-    if constexpr (AGG) tab = &agg;
+    AggOf<AGG>* tab = nullptr;
+    if constexpr (AGG > 0) tab = &agg;
     const double tsum = elem_tile<T, K, MODE, EPT, AGG>(a, (int64_t)lb * blockDim.x * EPT, n_items,
                                                         0, fb, tab);
     if constexpr (has_sum(MODE)) {
@@ -303,14 +303,17 @@ hipError_t launch_elem_t(const MeshView& m, const MeshPass& p, hipStream_t s) {
     const int64_t nb = mesh_blocks(n_items, p.block, EPT);
     if (nb == 0) return hipSuccess;
     // Combine in LDS when the workgroup's contributions fit the table twice over
-    // at worst (all distinct); meshes with locality fill it far less.
+    // at worst (all distinct); meshes with locality fill it far less.  The
+    // plan picks the table size (p.agg_slots) from simulated workgroups.
     const bool agg = is_atomic(MODE) && p.combine && (int64_t)p.block * EPT * K <= 2 * kAggSlots;
-    if (agg)
-        PG_LAUNCH((k_mesh_elem<T, K, MODE, EPT, true>), dim3((unsigned)nb), dim3(p.block), 0,
-                           s, m, p);
+    if (agg && p.agg_slots == kAggSlotsSmall && EPT == 1)
+        PG_LAUNCH((k_mesh_elem<T, K, MODE, EPT, kAggSlotsSmall>), dim3((unsigned)nb), dim3(p.block),
+                  0, s, m, p);
+    else if (agg)
+        PG_LAUNCH((k_mesh_elem<T, K, MODE, EPT, kAggSlots>), dim3((unsigned)nb), dim3(p.block), 0,
+                  s, m, p);
     else
-        PG_LAUNCH((k_mesh_elem<T, K, MODE, EPT, false>), dim3((unsigned)nb), dim3(p.block),
-                           0, s, m, p);
+        PG_LAUNCH((k_mesh_elem<T, K, MODE, EPT, 0>), dim3((unsigned)nb), dim3(p.block), 0, s, m, p);
     return hipGetLastError();
 }
 

@@ -652,7 +652,9 @@ pg_status pg_prog_bind_workspace(pg_prog p, void* ws, size_t bytes) {
             ptr.push_back(t.data());
             cnt.push_back((int64_t)t.size());
         }
-        g.hash_shift = tiles.empty() ? 2533u : choose_hash_shift(ptr.data(), cnt.data(), (int64_t)tiles.size());
+        g.hash_shift = tiles.empty() ? 2533u
+                                     : choose_hash_shift(ptr.data(), cnt.data(), (int64_t)tiles.size(),
+                                                         4096, nullptr);  // the group kernels' table
     }
     p->ws = static_cast<char*>(ws);
     return PG_OK;

@@ -84,6 +84,7 @@ def test_mesh_plan_is_host_only_and_sizes_workspace():
     (dict(opts="bad_adjoint"), P.EINVAL),
     (dict(opts="bad_block"), P.EINVAL),
     (dict(opts="bad_tile"), P.EINVAL),
+    (dict(opts="bad_scatter"), P.EINVAL),
 ])
 def test_mesh_plan_argument_errors(kw, code):
     if kw.get("opts") == "bad_adjoint":
@@ -92,6 +93,8 @@ def test_mesh_plan_argument_errors(kw, code):
         kw["opts"] = P.make_options(block=100)
     elif kw.get("opts") == "bad_tile":
         kw["opts"] = P.make_options(tile=3)
+    elif kw.get("opts") == "bad_scatter":
+        kw["opts"] = P.make_options(scatter=4)
     st, plan, _ = plan_mesh(**kw)
     assert st == code
     assert not plan.value

@@ -208,10 +208,11 @@ def test_hex128_full_size_parity():
 
 
 @pytest.mark.parametrize("name", ["hex23", "rand_k8", "rand_k4", "chain10k"])
-@pytest.mark.parametrize("scatter", [0, 1])
+@pytest.mark.parametrize("scatter", [0, 1, 2, 3])
 @pytest.mark.parametrize("block,tile", [(256, 1), (128, 2), (64, 4), (512, 1)])
 def test_scatter_combining(name, scatter, block, tile):
-    """Atomic adjoint with and without the per-workgroup LDS combining."""
+    """Atomic adjoint with and without the per-workgroup LDS combining
+    (plan-chosen table, direct atomics, 4096-slot and 2048-slot tables)."""
     m = MESHES[name]()
     obj, x = _obj(m, "f64", block=block, tile=tile, scatter=scatter)
     f, g = obj.gradient(x)
