@@ -219,3 +219,56 @@ def test_scatter_combining(name, scatter, block, tile):
     _check(m, f.item(), g.cpu().numpy())
     fbar = torch.tensor([1.75], dtype=torch.float64, device="cuda")
     _check(m, None, obj.adjoint(x, fbar).cpu().numpy(), fbar=1.75)
+
+
+@pytest.mark.parametrize("name", ["hex23", "rand_k5", "chain10k"])
+def test_f_is_written_every_call(name):
+    """Every objective and gradient call writes f, bitwise the same (the
+    fixed-order reduction), and the tangent is repeatable."""
+    m = MESHES[name]()
+    obj, x = _obj(m)
+    f = torch.empty((), dtype=torch.float64, device="cuda")
+    g = torch.empty_like(x)
+    obj.objective(x, f_out=f)
+    f0 = f.item()
+    assert srel(f0, _oracle_grad(m)[0]) <= TOL_F64_F
+    for i in range(40):
+        f.fill_(float("nan"))
+        if i % 2:
+            obj.objective(x, f_out=f)
+        else:
+            obj.gradient(x, out=g, f_out=f)
+        assert f.item() == f0, (i, f.item(), f0)
+    d = torch.ones_like(x)
+    j1 = obj.jvp(x, d).item()
+    j2 = obj.jvp(x, d).item()
+    assert j1 == j2 and np.isfinite(j1)
+
+
+def test_gradient_in_a_graph():
+    """Gradient (zero fill, element pass, final sum) captured in a HIP graph
+    and replayed, with f and the gradient cleared by eager work in between."""
+    import ctypes
+    from paper_2507_13204_amd import pgrad as P
+    m = MESHES["hex23"]()
+    obj, x = _obj(m)
+    g = torch.empty_like(x)
+    f = torch.empty((), dtype=torch.float64, device="cuda")
+    f_e, g_e = obj.gradient(x)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        obj.gradient(x, out=g, f_out=f)
+        with torch.cuda.graph(graph, stream=s):
+            P.check(P.lib().pg_gradient(obj._plan, P._ptr(x), P._ptr(g), P._ptr(f),
+                                        ctypes.c_void_p(s.cuda_stream)), "pg_gradient")
+    torch.cuda.current_stream().wait_stream(s)
+    for _ in range(3):
+        f.fill_(float("nan"))
+        g.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert f.item() == f_e.item()
+        _check(m, f.item(), g.cpu().numpy())
