@@ -291,9 +291,12 @@ pg_status pg_prog_bind_workspace(pg_prog prog, void* workspace, size_t bytes);
 /* inputs: host array of device pointers, one per input in creation order.
  * f_out: device FP64 (may be NULL).  grads: NULL (objective only) or a host
  * array with one device pointer per input (NULL entries skipped); each is
- * overwritten with df/d(input).  Enqueued on stream. */
+ * overwritten with fbar * df/d(input).  fbar: device FP64 seed of f (NULL
+ * means 1; the backward of an autograd function passes grad_output).
+ * Enqueued on stream; no host synchronisation, so a run can be captured in
+ * a HIP graph. */
 pg_status pg_prog_run(pg_prog prog, const double* const* inputs, double* f_out,
-                      double* const* grads, pg_stream stream);
+                      double* const* grads, const double* fbar, pg_stream stream);
 /* What the transformation produced (filled by pg_prog_info, host out). */
 typedef struct {
     int32_t fwd_kernels;      /* launches of the forward pass (shadow clearing not counted) */

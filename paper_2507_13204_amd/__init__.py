@@ -10,7 +10,7 @@ from __future__ import annotations
 import importlib
 
 __all__ = ["MeshObjective", "DenseObjective", "BatchedDense", "MeshBatch", "MeshFn", "DenseFn",
-           "BatchedDenseFn", "MeshBatchFn", "Laplace1D", "Program", "PgError", "lib"]
+           "BatchedDenseFn", "MeshBatchFn", "Laplace1D", "Program", "ProgramFn", "PgError", "lib"]
 
 
 def __getattr__(name):

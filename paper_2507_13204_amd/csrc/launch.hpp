@@ -298,7 +298,7 @@ struct GroupDev {
     const double* gsrc = nullptr;
     double* gsrc_shadow = nullptr;
     uint32_t hash_shift = 2533;
-    double seed = 1.0;
+    const double* seed = nullptr;  // device seed of f (nullptr means 1)
     const double* leaf[kGLeaves] = {};
     double* leaf_shadow[kGLeaves] = {};
     int32_t leaf_acc[kGLeaves] = {};

@@ -661,7 +661,7 @@ pg_status pg_prog_bind_workspace(pg_prog p, void* ws, size_t bytes) {
 }
 
 pg_status pg_prog_run(pg_prog p, const double* const* inputs, double* f_out, double* const* grads,
-                      pg_stream stream) {
+                      const double* fbar, pg_stream stream) {
     clear_error();
     if (!p) return perr(PG_EINVAL, "program is NULL");
     if (!p->planned || !p->ws) return perr(PG_ESTATE, "plan the program and bind a workspace first");
@@ -730,6 +730,7 @@ pg_status pg_prog_run(pg_prog p, const double* const* inputs, double* f_out, dou
         if (g.has_sum) {
             d.sum_slot = slot(p->sum_view);
             d.partials = partials;
+            d.seed = fbar;
         }
         if (g.gather >= 0) {
             const Op& go = ops[(size_t)g.gather];

@@ -342,7 +342,7 @@ __global__ void __launch_bounds__(BS) k_group(GroupDev g) {
     if constexpr (REV) {
         Slots<NS> a;
         if (ok) {
-            if (g.sum_slot >= 0) a.add(g.sum_slot, g.seed);
+            if (g.sum_slot >= 0) a.add(g.sum_slot, g.seed ? *g.seed : 1.0);
             for (int x = 0; x < g.n_exports; ++x)
                 if (g.export_shadow[x]) a.add(g.export_slot[x], g.export_shadow[x][i]);
             for (int j = g.n_ops - 1; j >= 0; --j) {

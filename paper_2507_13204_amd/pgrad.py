@@ -124,7 +124,7 @@ def lib():
     L.pg_prog_sum.argtypes = [_VP, _I32]
     L.pg_prog_plan.argtypes = [_VP, _SZP]
     L.pg_prog_bind_workspace.argtypes = [_VP, _VP, ctypes.c_size_t]
-    L.pg_prog_run.argtypes = [_VP, ctypes.POINTER(_VP), _VP, ctypes.POINTER(_VP), _VP]
+    L.pg_prog_run.argtypes = [_VP, ctypes.POINTER(_VP), _VP, ctypes.POINTER(_VP), _VP, _VP]
     L.pg_prog_fusion.argtypes = [_VP, _I32]
     L.pg_prog_info.argtypes = [_VP, ctypes.POINTER(ProgStats)]
     L.pg_prog_destroy.argtypes = [_VP]
@@ -591,9 +591,11 @@ class Program:
         check(lib().pg_prog_info(self._p, ctypes.byref(st)), "pg_prog_info")
         return {name: getattr(st, name) for name, _ in ProgStats._fields_}
 
-    def run(self, inputs: Sequence[torch.Tensor], grads=True, stream=None, f_out=None):
+    def run(self, inputs: Sequence[torch.Tensor], grads=True, stream=None, f_out=None,
+            fbar: Optional[torch.Tensor] = None):
         """f (0-d float64 tensor) and, when grads is True (or a list of output
-        tensors / None entries), the gradients with respect to the inputs."""
+        tensors / None entries), the gradients with respect to the inputs,
+        scaled by the device seed fbar (one float64; None means 1)."""
         if len(inputs) != self.n_inputs:
             raise PgError(EINVAL, "run", f"expected {self.n_inputs} inputs")
         for x, n in zip(inputs, self.input_lengths):
@@ -612,7 +614,12 @@ class Program:
         gp = None
         if outs is not None:
             gp = (_VP * max(self.n_inputs, 1))(*[None if g is None else g.data_ptr() for g in outs])
-        check(lib().pg_prog_run(self._p, ins, _ptr(f), gp, _stream(stream)), "pg_prog_run")
+        if fbar is not None:
+            _need_cuda(fbar)
+            if fbar.dtype != torch.float64 or fbar.numel() != 1:
+                raise PgError(EDTYPE, "run", "fbar: one float64 on the device")
+        check(lib().pg_prog_run(self._p, ins, _ptr(f), gp, _ptr(fbar), _stream(stream)),
+              "pg_prog_run")
         return (f, outs) if outs is not None else f
 
     def close(self):
@@ -662,6 +669,30 @@ class DenseFn(torch.autograd.Function):
         (x,) = ctx.saved_tensors
         fbar = gout.detach().to(torch.float64).contiguous().reshape(1)
         return ctx.obj.adjoint(x.detach().contiguous(), fbar), None
+
+
+class ProgramFn(torch.autograd.Function):
+    """f = ProgramFn.apply(program, *inputs) for a planned Program; the
+    backward runs the program's generated reverse pass seeded with
+    grad_output (its forward values are recomputed there, as the fused
+    groups do anyway)."""
+
+    @staticmethod
+    def forward(ctx, program: "Program", *inputs):
+        xs = [x.detach().contiguous() for x in inputs]
+        f = program.run(xs, grads=None)
+        ctx.program = program
+        ctx.save_for_backward(*xs)
+        return f
+
+    @staticmethod
+    def backward(ctx, gout):
+        xs = ctx.saved_tensors
+        fbar = gout.detach().to(torch.float64).contiguous().reshape(1)
+        want = [ctx.needs_input_grad[1 + i] for i in range(len(xs))]
+        outs = [torch.empty_like(x) if w else None for x, w in zip(xs, want)]
+        _, gs = ctx.program.run(list(xs), grads=outs, fbar=fbar)
+        return (None, *gs)
 
 
 class BatchedDenseFn(torch.autograd.Function):

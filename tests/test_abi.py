@@ -236,7 +236,7 @@ def test_program_plan_reports_the_generated_reverse_pass():
     assert L.pg_prog_bind_workspace(p, FAKE + 8, sz.value) == P.EWORKSPACE
     assert L.pg_prog_bind_workspace(p, FAKE, sz.value - 1) == P.EWORKSPACE
     ins = (ctypes.c_void_p * 1)(FAKE)
-    assert L.pg_prog_run(p, ins, None, None, None) == P.ESTATE       # no workspace bound
+    assert L.pg_prog_run(p, ins, None, None, None, None) == P.ESTATE  # no workspace bound
     L.pg_prog_destroy(p)
 
 

@@ -234,3 +234,68 @@ def test_mesh_program_full_size(fusion, orc):
     assert rel(g.cpu().numpy(), g_ref) < TOL_F64_G
     if fusion:
         assert prog.info()["fwd_kernels"] == 2 and prog.info()["rev_kernels"] == 0
+
+
+@pytest.mark.parametrize("fusion", FUSION)
+def test_seeded_run_scales_the_gradient(fusion):
+    case = inputs.program_mix(700, 500, 4, seed=13)
+    prog = P.Program.from_spec(case.spec, fusion=fusion).plan()
+    xs = [to_dev(x) for x in case.inputs]
+    f1, g1 = prog.run(xs)
+    fbar = torch.tensor([-2.5], dtype=torch.float64, device="cuda")
+    f2, g2 = prog.run(xs, fbar=fbar)
+    torch.cuda.synchronize()
+    assert f1.item() == f2.item()          # the seed scales gradients only
+    for a, b in zip(g1, g2):
+        assert rel(b.cpu().numpy(), -2.5 * a.cpu().numpy()) < 1e-15
+
+
+def test_program_autograd_matches_oracle_and_fd():
+    case = inputs.program_paper(300, seed=4)
+    prog = P.Program.from_spec(case.spec).plan()
+    x, b = [to_dev(v).requires_grad_(True) for v in case.inputs]
+    f = P.ProgramFn.apply(prog, x, b)
+    (3.0 * f).backward()
+    _, (gx_ref, gb_ref) = OP.gradient(case.spec, case.inputs)
+    assert rel(x.grad.cpu().numpy(), 3.0 * gx_ref) < TOL_F64_G
+    assert rel(b.grad.cpu().numpy(), 3.0 * gb_ref) < TOL_F64_G
+    # central differences of the objective along random directions
+    rng = np.random.default_rng(8)
+    for _ in range(4):
+        d = rng.standard_normal(300)
+        h = 1e-5
+        xp, xm = case.inputs[0] + h * d, case.inputs[0] - h * d
+        fp = prog.run([to_dev(xp), to_dev(case.inputs[1])], grads=None).item()
+        fm = prog.run([to_dev(xm), to_dev(case.inputs[1])], grads=None).item()
+        fd = (fp - fm) / (2 * h)
+        assert abs(fd - float(gx_ref @ d)) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_program_run_replays_from_a_graph():
+    """A fused program run (objective and gradient) captured in a HIP graph
+    and replayed; every replay matches the eager result."""
+    case = inputs.program_mix(1000, 777, 4, seed=7)
+    prog = P.Program.from_spec(case.spec).plan()
+    xs = [to_dev(x) for x in case.inputs]
+    f_e, g_e = prog.run(xs)
+    torch.cuda.synchronize()
+    f = torch.empty((), dtype=torch.float64, device="cuda")
+    gs = [torch.empty_like(x) for x in xs]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        prog.run(xs, grads=gs, f_out=f, stream=s)
+        with torch.cuda.graph(graph, stream=s):
+            prog.run(xs, grads=gs, f_out=f, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    for _ in range(3):
+        f.fill_(float("nan"))
+        for g in gs:
+            g.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert srel(f.item(), f_e.item()) < 1e-14
+        for a, b in zip(gs, g_e):
+            assert rel(a.cpu().numpy(), b.cpu().numpy()) < 1e-13
