@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--scatter", type=int, default=0, help="0 combine in LDS, 1 direct atomics")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=6.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", default="hex",
                     choices=["hex", "dense", "bdense", "batch", "chain", "paper", "program"],
                     help="hex (default, the headline), dense, bdense, batch, chain, paper, "
