@@ -138,24 +138,30 @@ k_dense_fused(DenseView d, const T* __restrict__ x, const double* __restrict__ f
     }
 }
 
-// grad[j] (=|+=) sum over bands g ascending of colpart[g, j].
+// grad[j] (=|+=) sum of colpart[g, j] over the bands: kColSlices slices of
+// consecutive bands, each summed in ascending order by one thread, then the
+// slices added in ascending order (deterministic).  32 columns per
+// workgroup so the launch covers the device even for 10^4 columns.
+constexpr int kColW = 32, kColSlices = 16;
+
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kColW * kColSlices)
 k_dense_colsum(const double* __restrict__ colpart, int ngroups, int64_t cols, T* __restrict__ grad,
                int accumulate) {
-    __shared__ double part[4][64];
-    const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    const int y = threadIdx.y;  // 4 slices of the bands, each summed in order
+    __shared__ double part[kColSlices][kColW];
+    const int64_t j = (int64_t)blockIdx.x * kColW + threadIdx.x;
+    const int y = threadIdx.y;
     double s = 0.0;
     if (j < cols) {
-        const int g0 = ngroups * y / 4, g1 = ngroups * (y + 1) / 4;
+        const int g0 = ngroups * y / kColSlices, g1 = ngroups * (y + 1) / kColSlices;
         for (int g = g0; g < g1; ++g) s += colpart[(int64_t)g * cols + j];
     }
     part[y][threadIdx.x] = s;
     __syncthreads();
     if (y == 0 && j < cols) {
-        const double t = ((part[0][threadIdx.x] + part[1][threadIdx.x]) + part[2][threadIdx.x]) +
-                         part[3][threadIdx.x];
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < kColSlices; ++q) t += part[q][threadIdx.x];
         grad[j] = accumulate ? static_cast<T>(to_f64(grad[j]) + t) : static_cast<T>(t);
     }
 }
@@ -244,7 +250,7 @@ hipError_t launch_dense_fused(const DenseView& d, const void* x, const double* f
 hipError_t launch_dense_colsum(const double* colpart, int ngroups, int64_t cols, void* grad,
                                Dtype dt, int accumulate, hipStream_t s) {
     if (cols == 0) return hipSuccess;
-    const dim3 grid((unsigned)((cols + 63) / 64)), block(64, 4);
+    const dim3 grid((unsigned)((cols + kColW - 1) / kColW)), block(kColW, kColSlices);
     if (dt == F64)
         hipLaunchKernelGGL(k_dense_colsum<double>, grid, block, 0, s, colpart, ngroups, cols,
                            (double*)grad, accumulate);
