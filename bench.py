@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--side", type=int, default=128, help="nodes per axis of the hex mesh")
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
-    ap.add_argument("--adjoint", default="atomic", choices=["atomic", "gather", "colour"])
+    ap.add_argument("--adjoint", default="atomic", choices=["atomic", "gather", "colour", "tiled"])
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--copies", type=int, default=3, help="rotating input copies")
@@ -240,7 +240,7 @@ def bench_hex(args):
 
     if not args.no_variants:
         variants = {}
-        for adj in ("atomic", "gather", "colour"):
+        for adj in ("atomic", "gather", "colour", "tiled"):
             if adj == args.adjoint:
                 continue
             o2 = MeshObjective(conn, B, w, m.n_nodes, adjoint=adj)

@@ -76,8 +76,16 @@ typedef enum {
     PG_ADJ_ATOMIC = 1, /* element-parallel scatter with FP64 atomic adds */
     PG_ADJ_GATHER = 2, /* deterministic: node-parallel gather over the
                           transposed (node -> element) connectivity */
-    PG_ADJ_COLOUR = 3  /* deterministic: element colour classes, one
+    PG_ADJ_COLOUR = 3, /* deterministic: element colour classes, one
                           non-atomic pass per colour */
+    PG_ADJ_TILED = 4   /* deterministic: each workgroup sums its tile's
+                          contributions per node in LDS in a fixed order
+                          (local incidence lists built at bind), then a
+                          node-parallel pass adds the tiles' partials in
+                          tile order; no atomics, no fill of grad.  Mesh
+                          plans only; the workspace is sized for the worst
+                          case (12 + 2 + 4 bytes per incidence more than the
+                          atomic plan). */
 } pg_adjoint_kind;
 
 /* What the forward pass keeps for the reverse pass (section 4: intermediates

@@ -177,7 +177,10 @@ struct pg_plan_s {
     size_t ws_bytes = 0;
     size_t o_partials = NONE, o_flag = NONE, o_u = NONE, o_v = NONE, o_offs = NONE,
            o_cursor = NONE, o_inc = NONE, o_scan = NONE, o_gacc = NONE, o_colpart = NONE,
-           o_tiles = NONE, o_vmat = NONE;
+           o_tiles = NONE, o_vmat = NONE, o_tbase = NONE, o_loff = NONE, o_lidx = NONE,
+           o_stage = NONE, o_noff = NONE, o_npos = NONE;
+    int tiled_tile = 0;       // elements per tile of the two-level deterministic adjoint
+    int64_t tiled_nt = 0;
     size_t n_partials = 0;
     char* ws = nullptr;
     bool bound = false;
@@ -204,7 +207,7 @@ constexpr int kDefaultBlock = 512;
 pg_status check_opts(const pg_options* o, pg_options* out) {
     *out = pg_default_options();
     if (o) *out = *o;
-    if (out->adjoint < PG_ADJ_AUTO || out->adjoint > PG_ADJ_COLOUR)
+    if (out->adjoint < PG_ADJ_AUTO || out->adjoint > PG_ADJ_TILED)
         return fail(PG_EINVAL, "options.adjoint %d is not a pg_adjoint_kind", out->adjoint);
     if (out->adjoint == PG_ADJ_AUTO) out->adjoint = PG_ADJ_ATOMIC;
     if (out->ckpt != PG_RECOMPUTE && out->ckpt != PG_STORE)
@@ -259,6 +262,21 @@ void layout_mesh(pg_plan_s* p) {
         p->o_cursor = L.take(sizeof(int32_t) * (size_t)m.n_nodes);
         p->o_inc = L.take(sizeof(int32_t) * (size_t)(m.n_elems * m.k));
         p->o_scan = L.take(sizeof(int64_t) * (size_t)scan_scratch_items(m.n_nodes));
+    }
+    if (p->opt.adjoint == PG_ADJ_TILED) {
+        // Sized for the worst case (every incidence its own local node); the
+        // actual counts are known only at bind, from the connectivity.
+        const int64_t inc = m.n_elems * m.k;
+        p->tiled_tile = tiled_tile_elems(p->opt.block, m.k);
+        p->tiled_nt = (m.n_elems + p->tiled_tile - 1) / p->tiled_tile;
+        p->n_partials = (size_t)std::max<int64_t>(std::max<int64_t>(p->mesh_blocks_n, p->tiled_nt), 1);
+        p->o_partials = L.take(sizeof(double) * p->n_partials);
+        p->o_tbase = L.take(sizeof(int64_t) * (size_t)(p->tiled_nt + 1));
+        p->o_loff = L.take(sizeof(int32_t) * (size_t)(inc + p->tiled_nt + 1));
+        p->o_lidx = L.take(sizeof(int16_t) * (size_t)std::max<int64_t>(inc, 1));
+        p->o_stage = L.take(sizeof(double) * (size_t)std::max<int64_t>(inc, 1));
+        p->o_noff = L.take(sizeof(int32_t) * (size_t)(m.n_nodes + 1));
+        p->o_npos = L.take(sizeof(int32_t) * (size_t)std::max<int64_t>(inc, 1));
     }
     if (p->opt.adjoint == PG_ADJ_COLOUR) {
         // One extra partial slot per colour class (a class ends a workgroup early).
@@ -442,6 +460,19 @@ MeshPass base_pass(pg_plan p, const void* x) {
 
 enum Want { W_OBJ = 1, W_GRAD = 2 };
 
+TiledView tiled_view(pg_plan p) {
+    TiledView v;
+    v.n_tiles = p->tiled_nt;
+    v.tile = p->tiled_tile;
+    v.tbase = p->at<int64_t>(p->o_tbase);
+    v.loff = p->at<int32_t>(p->o_loff);
+    v.lidx = p->at<int16_t>(p->o_lidx);
+    v.stage = p->at<double>(p->o_stage);
+    v.noff = p->at<int32_t>(p->o_noff);
+    v.npos = p->at<int32_t>(p->o_npos);
+    return v;
+}
+
 pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, double* f_out,
                    int want, hipStream_t s) {
     const MeshView& m = p->mesh;
@@ -487,6 +518,17 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
         if (f32)
             PG_HIP(launch_f64_to_f32(q.gacc, static_cast<float*>(grad), m.n_nodes, acc, s));
         if (obj && f_out) PG_HIP(launch_final_sum(q.partials, slot, f_out, s));
+        return PG_OK;
+    }
+    if (p->opt.adjoint == PG_ADJ_TILED) {
+        // Level 1 writes every tile's partials (and f's partials); level 2
+        // overwrites or adds to grad, so no fill is needed.
+        const TiledView tv = tiled_view(p);
+        PG_HIP(tmark(p, 1, true, s));
+        PG_HIP(launch_mesh_tiled(m, q, tv, obj, s));
+        PG_HIP(launch_node_tiled(m, tv, grad, acc, s));
+        PG_HIP(tmark(p, 1, false, s));
+        if (obj && f_out) PG_HIP(launch_final_sum(q.partials, p->tiled_nt, f_out, s));
         return PG_OK;
     }
     if (p->opt.adjoint == PG_ADJ_GATHER) {
@@ -568,6 +610,66 @@ void table_of(const std::vector<std::vector<int32_t>>& tiles, int* slots, uint32
     choose_table(ptr.data(), cnt.data(), (int64_t)tiles.size(), slots, shift);
 }
 
+// Structures of the two-level deterministic adjoint (on the host, at bind):
+// per tile its sorted distinct nodes and, per local node, the tile-relative
+// positions of its incidences in ascending order; per node, its staging
+// slots in ascending tile order.
+pg_status mesh_tiled_build(pg_plan p, hipStream_t s) {
+    const MeshView& m = p->mesh;
+    const int k = m.k, T = p->tiled_tile;
+    const int64_t E = m.n_elems, N = m.n_nodes, nt = p->tiled_nt, inc = E * k;
+    std::vector<int32_t> conn((size_t)inc);
+    if (inc > 0) {
+        PG_HIP(hipMemcpyAsync(conn.data(), m.conn, sizeof(int32_t) * (size_t)inc, hipMemcpyDeviceToHost, s));
+        PG_HIP(hipStreamSynchronize(s));
+    }
+    std::vector<int64_t> tbase((size_t)nt + 1, 0);
+    std::vector<int32_t> loff;
+    loff.reserve((size_t)(inc + nt + 1));
+    std::vector<int16_t> lidx((size_t)std::max<int64_t>(inc, 1));
+    std::vector<int32_t> stage_node;  // node of each staging slot
+    stage_node.reserve((size_t)inc);
+    std::vector<std::pair<int32_t, int32_t>> items;
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t e0 = t * T, e1 = std::min(E, e0 + T);
+        const int32_t cnt = (int32_t)((e1 - e0) * k);
+        items.resize((size_t)cnt);
+        for (int32_t q = 0; q < cnt; ++q) items[(size_t)q] = {conn[(size_t)(e0 * k + q)], q};
+        std::sort(items.begin(), items.end());  // by node, then by position
+        for (int32_t q = 0; q < cnt; ++q) {
+            if (q == 0 || items[(size_t)q].first != items[(size_t)q - 1].first) {
+                loff.push_back(q);
+                stage_node.push_back(items[(size_t)q].first);
+            }
+            lidx[(size_t)(e0 * k + q)] = (int16_t)items[(size_t)q].second;
+        }
+        loff.push_back(cnt);
+        tbase[(size_t)t + 1] = (int64_t)stage_node.size();
+    }
+    const int64_t S = (int64_t)stage_node.size();
+    // node -> staging slots, in ascending slot (hence tile) order
+    std::vector<int32_t> noff((size_t)N + 1, 0), npos((size_t)std::max<int64_t>(S, 1));
+    for (int64_t q = 0; q < S; ++q) noff[(size_t)stage_node[(size_t)q] + 1]++;
+    for (int64_t n = 0; n < N; ++n) noff[(size_t)n + 1] += noff[(size_t)n];
+    std::vector<int32_t> fill(noff.begin(), noff.end() - 1);
+    for (int64_t q = 0; q < S; ++q) npos[(size_t)fill[(size_t)stage_node[(size_t)q]]++] = (int32_t)q;
+    PG_HIP(hipMemcpyAsync(p->at<int64_t>(p->o_tbase), tbase.data(), sizeof(int64_t) * tbase.size(),
+                          hipMemcpyHostToDevice, s));
+    PG_HIP(hipMemcpyAsync(p->at<int32_t>(p->o_loff), loff.data(), sizeof(int32_t) * loff.size(),
+                          hipMemcpyHostToDevice, s));
+    if (inc > 0)
+        PG_HIP(hipMemcpyAsync(p->at<int16_t>(p->o_lidx), lidx.data(), sizeof(int16_t) * (size_t)inc,
+                              hipMemcpyHostToDevice, s));
+    PG_HIP(hipMemcpyAsync(p->at<int32_t>(p->o_noff), noff.data(), sizeof(int32_t) * noff.size(),
+                          hipMemcpyHostToDevice, s));
+    if (S > 0)
+        PG_HIP(hipMemcpyAsync(p->at<int32_t>(p->o_npos), npos.data(), sizeof(int32_t) * (size_t)S,
+                              hipMemcpyHostToDevice, s));
+    PG_HIP(hipStreamSynchronize(s));
+    return PG_OK;
+}
+
+
 // Greedy colouring in element order (plan time, on the host): element e
 // takes the smallest colour that no earlier element sharing one of its nodes
 // has.  Node masks record the colours already present at each node, so one
@@ -647,6 +749,10 @@ pg_status mesh_bind(pg_plan p, hipStream_t s) {
     if (p->opt.adjoint == PG_ADJ_COLOUR) {
         pg_status cst = mesh_colour(p, s);
         if (cst != PG_OK) return cst;
+    }
+    if (p->opt.adjoint == PG_ADJ_TILED) {
+        pg_status tst = mesh_tiled_build(p, s);
+        if (tst != PG_OK) return tst;
     }
     if (p->opt.adjoint == PG_ADJ_GATHER) {
         int32_t* offs = p->at<int32_t>(p->o_offs);
@@ -1122,7 +1228,8 @@ pg_status pg_laplace1d_plan(pg_plan* plan, int64_t n, pg_dtype dtype, const pg_o
     const int32_t want = opts ? opts->adjoint : PG_ADJ_AUTO;
     pg_options o;
     if ((st = check_opts(opts, &o))) return st;
-    if (want == PG_ADJ_COLOUR) return fail(PG_EUNSUPPORTED, "no colour schedule for this example");
+    if (want == PG_ADJ_COLOUR || want == PG_ADJ_TILED)
+        return fail(PG_EUNSUPPORTED, "no colour or tiled schedule for this example");
     if (n < 0 || n >= (1LL << 40)) return fail(PG_EINVAL, "n out of range");
     pg_plan_s* p = new_plan(K_LAPLACE, dtype, o);
     if (!p) return fail(PG_EINVAL, "out of host memory");

@@ -82,6 +82,30 @@ struct MeshPass {
 // Number of workgroups an element pass over n items launches.
 int64_t mesh_blocks(int64_t n_items, int block, int ept);
 
+// Plan-time structures of the two-level deterministic adjoint (tiled_kernels.hip):
+// tile t = elements [t * tile, (t + 1) * tile); its local nodes are the
+// distinct nodes it touches, in ascending order, with staging slots
+// tbase[t] .. tbase[t+1]-1; loff (at tbase[t] + t) holds, per local node, the
+// range of its incidences in lidx (tile-relative positions e_local * k + j,
+// ascending); noff / npos list, per node, its staging slots in ascending tile
+// order.
+struct TiledView {
+    int64_t n_tiles = 0;
+    int tile = 0;
+    const int64_t* tbase = nullptr;
+    const int32_t* loff = nullptr;
+    const int16_t* lidx = nullptr;
+    double* stage = nullptr;
+    const int32_t* noff = nullptr;
+    const int32_t* npos = nullptr;
+};
+int tiled_tile_elems(int block, int32_t k);
+// Level 1 (obj: with the objective partial per tile into p.partials) and level 2.
+hipError_t launch_mesh_tiled(const MeshView& m, const MeshPass& p, const TiledView& tv, bool obj,
+                             hipStream_t s);
+hipError_t launch_node_tiled(const MeshView& m, const TiledView& tv, void* grad, int accumulate,
+                             hipStream_t s);
+
 hipError_t launch_mesh_elem(const MeshView& m, MeshMode mode, const MeshPass& p, hipStream_t s);
 
 // Node-parallel gather of the reverse pass over the transposed connectivity:

@@ -1,0 +1,146 @@
+// Deterministic adjoint scatter in two fixed-order levels (no atomics).
+//
+// Level 1, one workgroup per tile of consecutive elements: each thread
+// writes its element's k contributions v_e B[e, j] into LDS; then, for every
+// node the tile touches (its "local nodes", known from the plan), one thread
+// adds that node's contributions from LDS in ascending (element, corner)
+// order and writes the tile's partial for the node to a staging array.
+// Level 2, one thread per node: the node's partials from the tiles that touch
+// it are added in ascending tile order, overwriting (or adding to) grad.
+// Every sum has a fixed order, so the gradient is bitwise repeatable; the
+// staging writes are coalesced and no zero fill of grad is needed.  This is
+// the conclusion's "reschedule the reverse threads" remedy applied at the
+// workgroup level, with the workgroup-local reschedule done in LDS.
+#include "device_common.hpp"
+#include "elem_tile.hpp"
+#include "launch.hpp"
+
+namespace pg {
+
+namespace {
+
+// OBJ: also the objective partial per tile.  K > 0: row length known at
+// compile time (rows in registers, vector loads); K == 0: runtime m.k.
+template <typename T, int K, bool OBJ>
+__global__ void __launch_bounds__(1024)
+k_mesh_tiled(MeshView m, MeshPass p, TiledView tv) {
+    extern __shared__ double c_lds[];
+    __shared__ double lds[16];
+    const T* __restrict__ B = static_cast<const T*>(m.B);
+    const T* __restrict__ W = static_cast<const T*>(m.w);
+    const T* __restrict__ X = static_cast<const T*>(p.x);
+    const int k = K > 0 ? K : m.k;
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t e0 = t * blockDim.x, e = e0 + threadIdx.x;
+    const bool ok = e < m.n_elems;
+    const double fb = p.fbar ? p.fbar[0] : 1.0;
+    double tsum = 0.0;
+    if constexpr (K > 0) {
+        int32_t cr[K];
+        T br[K];
+        double u = 0.0, wd = 0.0;
+        if (ok) {
+            load_conn_row<T, K>(m.conn, e, cr);
+            load_b_row<K>(B, e, br);
+            wd = to_f64(W[e]);
+            if (p.u_in) {
+                u = p.u_in[e];
+            } else {
+                T xv[K];
+#pragma unroll
+                for (int j = 0; j < K; ++j) xv[j] = X[cr[j]];
+#pragma unroll
+                for (int j = 0; j < K; ++j) u += to_f64(br[j]) * to_f64(xv[j]);
+            }
+        }
+        const double s2 = u * u;
+        if constexpr (OBJ) tsum = wd * psi_from_sq(s2);
+        const double v = fb * wd * dpsi_from(u, s2);
+#pragma unroll
+        for (int j = 0; j < K; ++j) c_lds[threadIdx.x * K + j] = ok ? v * to_f64(br[j]) : 0.0;
+    } else {
+        double u = 0.0, wd = 0.0;
+        if (ok) {
+            wd = to_f64(W[e]);
+            if (p.u_in) {
+                u = p.u_in[e];
+            } else {
+                for (int j = 0; j < k; ++j) u += to_f64(B[e * k + j]) * to_f64(X[m.conn[e * k + j]]);
+            }
+        }
+        const double s2 = u * u;
+        if constexpr (OBJ) tsum = wd * psi_from_sq(s2);
+        const double v = fb * wd * dpsi_from(u, s2);
+        for (int j = 0; j < k; ++j) c_lds[threadIdx.x * k + j] = ok ? v * to_f64(B[e * k + j]) : 0.0;
+    }
+    __syncthreads();
+    // The tile's local nodes: partial sums in ascending (element, corner) order.
+    const int64_t sb = tv.tbase[t], nl = tv.tbase[t + 1] - sb;
+    const int32_t* __restrict__ off = tv.loff + sb + t;
+    const int16_t* __restrict__ li = tv.lidx + e0 * k;
+    for (int64_t l = threadIdx.x; l < nl; l += blockDim.x) {
+        double s = 0.0;
+        for (int32_t q = off[l]; q < off[l + 1]; ++q) s += c_lds[li[q]];
+        tv.stage[sb + l] = s;
+    }
+    if constexpr (OBJ) {
+        const double s = block_sum_dyn(tsum, lds);
+        if (threadIdx.x == 0) p.partials[t] = s;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_node_tiled(int64_t n_nodes, const int32_t* __restrict__ noff, const int32_t* __restrict__ npos,
+             const double* __restrict__ stage, T* __restrict__ grad, int accumulate) {
+    const int64_t n = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (n >= n_nodes) return;
+    double s = 0.0;
+    for (int32_t q = noff[n]; q < noff[n + 1]; ++q) s += stage[npos[q]];
+    grad[n] = accumulate ? static_cast<T>(to_f64(grad[n]) + s) : static_cast<T>(s);
+}
+
+template <typename T, bool OBJ>
+hipError_t launch_tiled_t(const MeshView& m, const MeshPass& p, const TiledView& tv, hipStream_t s) {
+    const dim3 grid((unsigned)tv.n_tiles), block(tv.tile);
+    const size_t shmem = sizeof(double) * (size_t)tv.tile * (size_t)m.k;
+    switch (m.k) {
+        case 2: PG_LAUNCH((k_mesh_tiled<T, 2, OBJ>), grid, block, shmem, s, m, p, tv); break;
+        case 4: PG_LAUNCH((k_mesh_tiled<T, 4, OBJ>), grid, block, shmem, s, m, p, tv); break;
+        case 8: PG_LAUNCH((k_mesh_tiled<T, 8, OBJ>), grid, block, shmem, s, m, p, tv); break;
+        default: PG_LAUNCH((k_mesh_tiled<T, 0, OBJ>), grid, block, shmem, s, m, p, tv); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int tiled_tile_elems(int block, int32_t k) {
+    // The LDS holds tile * k doubles (at most 32 KiB); positions fit int16.
+    int t = (4096 / k) / 64 * 64;
+    if (t < 64) t = 64;
+    return block < t ? block : t;
+}
+
+hipError_t launch_mesh_tiled(const MeshView& m, const MeshPass& p, const TiledView& tv, bool obj,
+                             hipStream_t s) {
+    if (tv.n_tiles == 0) return hipSuccess;
+    if (m.dtype == F64)
+        return obj ? launch_tiled_t<double, true>(m, p, tv, s) : launch_tiled_t<double, false>(m, p, tv, s);
+    return obj ? launch_tiled_t<float, true>(m, p, tv, s) : launch_tiled_t<float, false>(m, p, tv, s);
+}
+
+hipError_t launch_node_tiled(const MeshView& m, const TiledView& tv, void* grad, int accumulate,
+                             hipStream_t s) {
+    if (m.n_nodes == 0) return hipSuccess;
+    const dim3 grid((unsigned)((m.n_nodes + 255) / 256)), block(256);
+    if (m.dtype == F64)
+        hipLaunchKernelGGL(k_node_tiled<double>, grid, block, 0, s, m.n_nodes, tv.noff, tv.npos, tv.stage,
+                           (double*)grad, accumulate);
+    else
+        hipLaunchKernelGGL(k_node_tiled<float>, grid, block, 0, s, m.n_nodes, tv.noff, tv.npos, tv.stage,
+                           (float*)grad, accumulate);
+    return hipGetLastError();
+}
+
+}  // namespace pg

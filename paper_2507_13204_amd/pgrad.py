@@ -23,11 +23,12 @@ OK, EINVAL, ERANGE, EDTYPE, EALIAS, EWORKSPACE, EHIP, EUNSUPPORTED, ESTATE = ran
 STATUS_NAMES = ["PG_OK", "PG_EINVAL", "PG_ERANGE", "PG_EDTYPE", "PG_EALIAS", "PG_EWORKSPACE",
                 "PG_EHIP", "PG_EUNSUPPORTED", "PG_ESTATE"]
 F64, F32 = 0, 1
-ADJ_AUTO, ADJ_ATOMIC, ADJ_GATHER, ADJ_COLOUR = 0, 1, 2, 3
+ADJ_AUTO, ADJ_ATOMIC, ADJ_GATHER, ADJ_COLOUR, ADJ_TILED = 0, 1, 2, 3, 4
 RECOMPUTE, STORE = 0, 1
 WORKSPACE_ALIGN = 256
 
-ADJOINTS = {"auto": ADJ_AUTO, "atomic": ADJ_ATOMIC, "gather": ADJ_GATHER, "colour": ADJ_COLOUR}
+ADJOINTS = {"auto": ADJ_AUTO, "atomic": ADJ_ATOMIC, "gather": ADJ_GATHER, "colour": ADJ_COLOUR,
+            "tiled": ADJ_TILED}
 CKPTS = {"recompute": RECOMPUTE, "store": STORE}
 
 EXPORTS = ("pg_default_options", "pg_mesh_plan", "pg_dense_plan", "pg_bdense_plan",

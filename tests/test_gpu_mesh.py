@@ -11,7 +11,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 VARIANTS = [("atomic", "recompute"), ("atomic", "store"), ("gather", "recompute"),
-            ("gather", "store"), ("colour", "recompute"), ("colour", "store")]
+            ("gather", "store"), ("colour", "recompute"), ("colour", "store"),
+            ("tiled", "recompute"), ("tiled", "store")]
 
 
 def _obj(m, dtype="f64", **kw):
@@ -69,7 +70,7 @@ def test_mesh_launch_shapes(tile, block):
 
 
 @pytest.mark.parametrize("name", ["hex17", "rand_k8", "rand_k5", "chain10k"])
-@pytest.mark.parametrize("adj", ["atomic", "gather", "colour"])
+@pytest.mark.parametrize("adj", ["atomic", "gather", "colour", "tiled"])
 def test_mesh_gradient_parity_f32(name, adj):
     m = MESHES[name]()
     obj, x = _obj(m, "f32", adjoint=adj)
@@ -103,7 +104,7 @@ def test_accumulate_adds_into_grad():
         assert rel(g.cpu().numpy(), base.cpu().numpy() + g_ref) <= TOL_F64_G
 
 
-@pytest.mark.parametrize("adj", ["gather", "colour"])
+@pytest.mark.parametrize("adj", ["gather", "colour", "tiled"])
 def test_deterministic_variants_are_bitwise_repeatable(adj):
     m = inputs.hex_mesh(31, seed=14)
     obj, x = _obj(m, "f64", adjoint=adj)
@@ -151,7 +152,7 @@ def test_degenerate_meshes():
     # one node, one element using it twice
     m = inputs.Mesh(1, 1, 2, np.array([[0, 0]], np.int32), np.array([[1.0, 2.0]]),
                     np.array([1.0]), np.array([0.5]))
-    for adj in ("atomic", "gather", "colour"):
+    for adj in ("atomic", "gather", "colour", "tiled"):
         o, xx = _obj(m, adjoint=adj)
         f, g = o.gradient(xx)
         _check(m, f.item(), g.cpu().numpy())
@@ -272,3 +273,21 @@ def test_gradient_in_a_graph():
         torch.cuda.synchronize()
         assert f.item() == f_e.item()
         _check(m, f.item(), g.cpu().numpy())
+
+
+@pytest.mark.parametrize("block", [64, 256, 512, 1024])
+@pytest.mark.parametrize("name", ["hex23", "rand_k5", "rand_k8"])
+def test_tiled_adjoint_tile_sizes(name, block):
+    """The two-level deterministic adjoint over tile sizes (the tile is the
+    workgroup, capped so its LDS contributions fit), with a seed and
+    accumulation into an existing gradient."""
+    m = MESHES[name]()
+    obj, x = _obj(m, adjoint="tiled", block=block)
+    f, g = obj.gradient(x)
+    _check(m, f.item(), g.cpu().numpy())
+    fbar = torch.tensor([0.5], dtype=torch.float64, device="cuda")
+    _check(m, None, obj.adjoint(x, fbar).cpu().numpy(), fbar=0.5)
+    acc, _ = _obj(m, adjoint="tiled", block=block, accumulate=True)
+    g2 = g.clone()
+    acc.gradient(x, out=g2)
+    assert rel(g2.cpu().numpy(), 2.0 * g.cpu().numpy()) <= 1e-15
