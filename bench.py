@@ -66,6 +66,16 @@ def parse():
     return ap.parse_args()
 
 
+# What the library's event hook times per gradient call, by adjoint schedule:
+# one kernel for the atomic scatter, the range of the call's kernels otherwise.
+HEX_KERNELS = {
+    "atomic": "k_mesh_elem (gradient, atomic scatter with LDS combining)",
+    "gather": "k_mesh_elem + k_mesh_node_gather (range)",
+    "colour": "k_mesh_elem colour passes (range)",
+    "tiled": "k_mesh_tiled + k_node_tiled (range)",
+}
+
+
 def traffic_record(kernel_key: str):
     """HBM bytes per launch of the dominant kernel, measured with rocprofv3
     byte counters (profiles/traffic.json), or None if the kernel sources have
@@ -202,7 +212,7 @@ def bench_hex(args):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic,
-                     "kernel": f"k_mesh_elem (gradient, {args.adjoint})",
+                     "kernel": HEX_KERNELS[args.adjoint],
                      "kernel_ms": round(kms_grad, 5),
                      "algorithmic_bytes": int(gbytes * 1e9)},
     }

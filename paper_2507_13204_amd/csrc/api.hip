@@ -204,6 +204,10 @@ namespace {
 // their node rows in the LDS table); it is also the default elsewhere.
 constexpr int kDefaultBlock = 512;
 
+// Entries per tile of the int16 local-node offsets: at most tile * k + 1 are
+// used; the rest pads every tile to whole 16-byte chunks.
+int tiled_stride(const pg_plan_s* p) { return p->tiled_tile * p->mesh.k + 8; }
+
 pg_status check_opts(const pg_options* o, pg_options* out) {
     *out = pg_default_options();
     if (o) *out = *o;
@@ -272,7 +276,7 @@ void layout_mesh(pg_plan_s* p) {
         p->n_partials = (size_t)std::max<int64_t>(std::max<int64_t>(p->mesh_blocks_n, p->tiled_nt), 1);
         p->o_partials = L.take(sizeof(double) * p->n_partials);
         p->o_tbase = L.take(sizeof(int64_t) * (size_t)(p->tiled_nt + 1));
-        p->o_loff = L.take(sizeof(int32_t) * (size_t)(inc + p->tiled_nt + 1));
+        p->o_loff = L.take(sizeof(int16_t) * (size_t)p->tiled_nt * (size_t)tiled_stride(p));
         p->o_lidx = L.take(sizeof(int16_t) * (size_t)std::max<int64_t>(inc, 1));
         p->o_stage = L.take(sizeof(double) * (size_t)std::max<int64_t>(inc, 1));
         p->o_noff = L.take(sizeof(int32_t) * (size_t)(m.n_nodes + 1));
@@ -465,7 +469,8 @@ TiledView tiled_view(pg_plan p) {
     v.n_tiles = p->tiled_nt;
     v.tile = p->tiled_tile;
     v.tbase = p->at<int64_t>(p->o_tbase);
-    v.loff = p->at<int32_t>(p->o_loff);
+    v.lstride = tiled_stride(p);
+    v.loff = p->at<int16_t>(p->o_loff);
     v.lidx = p->at<int16_t>(p->o_lidx);
     v.stage = p->at<double>(p->o_stage);
     v.noff = p->at<int32_t>(p->o_noff);
@@ -624,8 +629,8 @@ pg_status mesh_tiled_build(pg_plan p, hipStream_t s) {
         PG_HIP(hipStreamSynchronize(s));
     }
     std::vector<int64_t> tbase((size_t)nt + 1, 0);
-    std::vector<int32_t> loff;
-    loff.reserve((size_t)(inc + nt + 1));
+    const int ls = tiled_stride(p);
+    std::vector<int16_t> loff((size_t)std::max<int64_t>(nt * ls, 1), 0);
     std::vector<int16_t> lidx((size_t)std::max<int64_t>(inc, 1));
     std::vector<int32_t> stage_node;  // node of each staging slot
     stage_node.reserve((size_t)inc);
@@ -633,17 +638,19 @@ pg_status mesh_tiled_build(pg_plan p, hipStream_t s) {
     for (int64_t t = 0; t < nt; ++t) {
         const int64_t e0 = t * T, e1 = std::min(E, e0 + T);
         const int32_t cnt = (int32_t)((e1 - e0) * k);
+        int16_t* lo = loff.data() + (size_t)(t * ls);
+        int32_t nl = 0;
         items.resize((size_t)cnt);
         for (int32_t q = 0; q < cnt; ++q) items[(size_t)q] = {conn[(size_t)(e0 * k + q)], q};
         std::sort(items.begin(), items.end());  // by node, then by position
         for (int32_t q = 0; q < cnt; ++q) {
             if (q == 0 || items[(size_t)q].first != items[(size_t)q - 1].first) {
-                loff.push_back(q);
+                lo[nl++] = (int16_t)q;
                 stage_node.push_back(items[(size_t)q].first);
             }
             lidx[(size_t)(e0 * k + q)] = (int16_t)items[(size_t)q].second;
         }
-        loff.push_back(cnt);
+        lo[nl] = (int16_t)cnt;
         tbase[(size_t)t + 1] = (int64_t)stage_node.size();
     }
     const int64_t S = (int64_t)stage_node.size();
@@ -655,8 +662,9 @@ pg_status mesh_tiled_build(pg_plan p, hipStream_t s) {
     for (int64_t q = 0; q < S; ++q) npos[(size_t)fill[(size_t)stage_node[(size_t)q]]++] = (int32_t)q;
     PG_HIP(hipMemcpyAsync(p->at<int64_t>(p->o_tbase), tbase.data(), sizeof(int64_t) * tbase.size(),
                           hipMemcpyHostToDevice, s));
-    PG_HIP(hipMemcpyAsync(p->at<int32_t>(p->o_loff), loff.data(), sizeof(int32_t) * loff.size(),
-                          hipMemcpyHostToDevice, s));
+    if (nt > 0)
+        PG_HIP(hipMemcpyAsync(p->at<int16_t>(p->o_loff), loff.data(), sizeof(int16_t) * (size_t)(nt * ls),
+                              hipMemcpyHostToDevice, s));
     if (inc > 0)
         PG_HIP(hipMemcpyAsync(p->at<int16_t>(p->o_lidx), lidx.data(), sizeof(int16_t) * (size_t)inc,
                               hipMemcpyHostToDevice, s));

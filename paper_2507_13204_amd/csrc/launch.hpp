@@ -85,21 +85,24 @@ int64_t mesh_blocks(int64_t n_items, int block, int ept);
 // Plan-time structures of the two-level deterministic adjoint (tiled_kernels.hip):
 // tile t = elements [t * tile, (t + 1) * tile); its local nodes are the
 // distinct nodes it touches, in ascending order, with staging slots
-// tbase[t] .. tbase[t+1]-1; loff (at tbase[t] + t) holds, per local node, the
-// range of its incidences in lidx (tile-relative positions e_local * k + j,
-// ascending); noff / npos list, per node, its staging slots in ascending tile
-// order.
+// tbase[t] .. tbase[t+1]-1; loff (tile t's entries at t * lstride, int16,
+// tile-relative) holds, per local node, the range of its incidences in lidx
+// (tile-relative positions e_local * k + j, ascending); noff / npos list, per
+// node, its staging slots in ascending tile order.
 struct TiledView {
     int64_t n_tiles = 0;
     int tile = 0;
+    int lstride = 0;  // tile * k + 8: room for nl + 1 offsets read as 16-byte chunks
     const int64_t* tbase = nullptr;
-    const int32_t* loff = nullptr;
+    const int16_t* loff = nullptr;
     const int16_t* lidx = nullptr;
     double* stage = nullptr;
     const int32_t* noff = nullptr;
     const int32_t* npos = nullptr;
 };
 int tiled_tile_elems(int block, int32_t k);
+// Dynamic LDS of one level-1 workgroup: contributions, positions and offsets.
+size_t tiled_lds_bytes(int tile, int32_t k);
 // Level 1 (obj: with the objective partial per tile into p.partials) and level 2.
 hipError_t launch_mesh_tiled(const MeshView& m, const MeshPass& p, const TiledView& tv, bool obj,
                              hipStream_t s);

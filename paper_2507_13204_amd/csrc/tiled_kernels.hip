@@ -19,8 +19,18 @@ namespace pg {
 
 namespace {
 
+// The tile's local-node offsets, tile-relative, as 16-byte chunks: at most
+// two chunks per thread for k <= 8 (nl + 1 <= tile * k + 1 entries).
+struct OffChunks {
+    typedef short v8 __attribute__((ext_vector_type(8)));
+    v8 c[2];
+};
+
 // OBJ: also the objective partial per tile.  K > 0: row length known at
 // compile time (rows in registers, vector loads); K == 0: runtime m.k.
+// The tile's positions and offsets are loaded first, with the element rows,
+// and land in LDS beside the contributions, so the per-node sums below touch
+// LDS only.
 template <typename T, int K, bool OBJ>
 __global__ void __launch_bounds__(1024)
 k_mesh_tiled(MeshView m, MeshPass p, TiledView tv) {
@@ -30,12 +40,29 @@ k_mesh_tiled(MeshView m, MeshPass p, TiledView tv) {
     const T* __restrict__ W = static_cast<const T*>(m.w);
     const T* __restrict__ X = static_cast<const T*>(p.x);
     const int k = K > 0 ? K : m.k;
+    const int cap = tv.tile * k;
+    int16_t* li_lds = reinterpret_cast<int16_t*>(c_lds + cap);
+    int16_t* lo_lds = li_lds + cap;
     const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t e0 = t * blockDim.x, e = e0 + threadIdx.x;
     const bool ok = e < m.n_elems;
+    const int64_t sb = tv.tbase[t];
+    const int nl = (int)(tv.tbase[t + 1] - sb);
+    const int16_t* __restrict__ li = tv.lidx + e0 * k;
+    const int16_t* __restrict__ lo = tv.loff + t * (int64_t)tv.lstride;
     const double fb = p.fbar ? p.fbar[0] : 1.0;
     double tsum = 0.0;
     if constexpr (K > 0) {
+        typedef short vk __attribute__((ext_vector_type(K)));
+        static_assert(K <= 8, "two offset chunks per thread cover tile * K + 1 entries for K <= 8");
+        vk pos{};
+        if (ok) pos = *reinterpret_cast<const vk*>(li + (int64_t)threadIdx.x * K);
+        OffChunks oc;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int c = (int)threadIdx.x + r * (int)blockDim.x;
+            if (c * 8 <= nl) oc.c[r] = *reinterpret_cast<const OffChunks::v8*>(lo + c * 8);
+        }
         int32_t cr[K];
         T br[K];
         double u = 0.0, wd = 0.0;
@@ -58,7 +85,16 @@ k_mesh_tiled(MeshView m, MeshPass p, TiledView tv) {
         const double v = fb * wd * dpsi_from(u, s2);
 #pragma unroll
         for (int j = 0; j < K; ++j) c_lds[threadIdx.x * K + j] = ok ? v * to_f64(br[j]) : 0.0;
+        if (ok) *reinterpret_cast<vk*>(li_lds + threadIdx.x * K) = pos;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int c = (int)threadIdx.x + r * (int)blockDim.x;
+            if (c * 8 <= nl) *reinterpret_cast<OffChunks::v8*>(lo_lds + c * 8) = oc.c[r];
+        }
     } else {
+        const int cnt = (int)((m.n_elems - e0 < (int64_t)blockDim.x ? m.n_elems - e0 : blockDim.x) * k);
+        for (int q = threadIdx.x; q < cnt; q += blockDim.x) li_lds[q] = li[q];
+        for (int q = threadIdx.x; q <= nl; q += blockDim.x) lo_lds[q] = lo[q];
         double u = 0.0, wd = 0.0;
         if (ok) {
             wd = to_f64(W[e]);
@@ -75,12 +111,10 @@ k_mesh_tiled(MeshView m, MeshPass p, TiledView tv) {
     }
     __syncthreads();
     // The tile's local nodes: partial sums in ascending (element, corner) order.
-    const int64_t sb = tv.tbase[t], nl = tv.tbase[t + 1] - sb;
-    const int32_t* __restrict__ off = tv.loff + sb + t;
-    const int16_t* __restrict__ li = tv.lidx + e0 * k;
-    for (int64_t l = threadIdx.x; l < nl; l += blockDim.x) {
+    for (int l = threadIdx.x; l < nl; l += blockDim.x) {
         double s = 0.0;
-        for (int32_t q = off[l]; q < off[l + 1]; ++q) s += c_lds[li[q]];
+        const int q1 = lo_lds[l + 1];
+        for (int q = lo_lds[l]; q < q1; ++q) s += c_lds[li_lds[q]];
         tv.stage[sb + l] = s;
     }
     if constexpr (OBJ) {
@@ -89,21 +123,34 @@ k_mesh_tiled(MeshView m, MeshPass p, TiledView tv) {
     }
 }
 
+// Slots are taken four at a time so that their loads are in flight together;
+// the additions stay in ascending slot order.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_node_tiled(int64_t n_nodes, const int32_t* __restrict__ noff, const int32_t* __restrict__ npos,
              const double* __restrict__ stage, T* __restrict__ grad, int accumulate) {
     const int64_t n = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (n >= n_nodes) return;
+    const int32_t q0 = noff[n], q1 = noff[n + 1];
     double s = 0.0;
-    for (int32_t q = noff[n]; q < noff[n + 1]; ++q) s += stage[npos[q]];
+    for (int32_t q = q0; q < q1; q += 4) {
+        int32_t pp[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pp[r] = q + r < q1 ? npos[q + r] : -1;
+        double v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = pp[r] >= 0 ? stage[pp[r]] : 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (pp[r] >= 0) s += v[r];
+    }
     grad[n] = accumulate ? static_cast<T>(to_f64(grad[n]) + s) : static_cast<T>(s);
 }
 
 template <typename T, bool OBJ>
 hipError_t launch_tiled_t(const MeshView& m, const MeshPass& p, const TiledView& tv, hipStream_t s) {
     const dim3 grid((unsigned)tv.n_tiles), block(tv.tile);
-    const size_t shmem = sizeof(double) * (size_t)tv.tile * (size_t)m.k;
+    const size_t shmem = tiled_lds_bytes(tv.tile, m.k);
     switch (m.k) {
         case 2: PG_LAUNCH((k_mesh_tiled<T, 2, OBJ>), grid, block, shmem, s, m, p, tv); break;
         case 4: PG_LAUNCH((k_mesh_tiled<T, 4, OBJ>), grid, block, shmem, s, m, p, tv); break;
@@ -115,8 +162,14 @@ hipError_t launch_tiled_t(const MeshView& m, const MeshPass& p, const TiledView&
 
 }  // namespace
 
+size_t tiled_lds_bytes(int tile, int32_t k) {
+    const size_t cap = (size_t)tile * (size_t)k;
+    return sizeof(double) * cap + sizeof(int16_t) * cap + sizeof(int16_t) * (cap + 8);
+}
+
 int tiled_tile_elems(int block, int32_t k) {
-    // The LDS holds tile * k doubles (at most 32 KiB); positions fit int16.
+    // The LDS holds tile * k doubles (at most 32 KiB) with their int16
+    // positions and offsets (tile * k <= 4096 for k <= 32).
     int t = (4096 / k) / 64 * 64;
     if (t < 64) t = 64;
     return block < t ? block : t;
