@@ -196,7 +196,7 @@ def test_chain_sweep(n):
 def test_hex128_full_size_parity():
     """128^3 nodes, 127^3 elements, in the launch configuration of the benchmark."""
     m = inputs.hex_mesh(128)
-    for adj in ("atomic", "gather", "colour"):
+    for adj in ("atomic", "gather", "colour", "tiled"):
         obj, x = _obj(m, "f64", adjoint=adj)
         f, g = obj.gradient(x)
         _check(m, f.item(), g.cpu().numpy())
