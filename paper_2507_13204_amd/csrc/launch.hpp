@@ -325,6 +325,7 @@ struct GroupDev {
     const double* gsrc = nullptr;
     double* gsrc_shadow = nullptr;
     uint32_t hash_shift = 2533;
+    int agg_slots = 4096;  // LDS table of the fused gather's scatter: 4096 or 2048
     const double* seed = nullptr;  // device seed of f (nullptr means 1)
     const double* leaf[kGLeaves] = {};
     double* leaf_shadow[kGLeaves] = {};

@@ -73,6 +73,7 @@ struct Group {
     bool sealed = false, has_sum = false;
     int32_t pos = 0;      // schedule position: its last member (the end for a sum-only group)
     uint32_t hash_shift = 2533;
+    int agg_slots = 4096;
 };
 
 // One step of the forward schedule: a non-pointwise construct or a group.
@@ -631,7 +632,8 @@ pg_status pg_prog_bind_workspace(pg_prog p, void* ws, size_t bytes) {
     }
     PG_HIP(hipMemcpy(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost));
     if (hflag) return perr(PG_ERANGE, "segment offsets are not 0 = o_0 <= ... <= o_n_seg = length");
-    // LDS hash rotation of each fused gather's scatter, chosen on sampled workgroups.
+    // LDS table size and hash rotation of each fused gather's scatter, chosen
+    // on sampled workgroups.
     for (Group& g : p->groups) {
         if (g.gather < 0) continue;
         const Op& op = p->ops[(size_t)g.gather];
@@ -652,9 +654,8 @@ pg_status pg_prog_bind_workspace(pg_prog p, void* ws, size_t bytes) {
             ptr.push_back(t.data());
             cnt.push_back((int64_t)t.size());
         }
-        g.hash_shift = tiles.empty() ? 2533u
-                                     : choose_hash_shift(ptr.data(), cnt.data(), (int64_t)tiles.size(),
-                                                         4096, nullptr);  // the group kernels' table
+        if (!tiles.empty())
+            choose_table(ptr.data(), cnt.data(), (int64_t)tiles.size(), &g.agg_slots, &g.hash_shift);
     }
     p->ws = static_cast<char*>(ws);
     return PG_OK;
@@ -741,6 +742,7 @@ pg_status pg_prog_run(pg_prog p, const double* const* inputs, double* f_out, dou
             d.gsrc = val[(size_t)go.a];
             d.gsrc_shadow = ops[(size_t)go.a].active ? shd[(size_t)go.a] : nullptr;
             d.hash_shift = g.hash_shift;
+            d.agg_slots = g.agg_slots;
             if (g.export_gather) {
                 d.export_slot[d.n_exports] = d.gather_slot;
                 d.export_val[d.n_exports] = at(p, go.val_off);

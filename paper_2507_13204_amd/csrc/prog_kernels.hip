@@ -275,15 +275,17 @@ struct GatherRow {
     double b[N];
 };
 
-// K: fused gather row length (0 none, -1 generic); NS: slots; BS: workgroup.
-template <int K, int MODE, int BS, int NS>
+// K: fused gather row length (0 none, -1 generic); NS: slots; BS: workgroup;
+// S: slots of the LDS table of the fused gather's scatter (0 without one).
+template <int K, int MODE, int BS, int NS, int S>
 __global__ void __launch_bounds__(BS) k_group(GroupDev g) {
     constexpr bool REV = MODE != G_FWD;
     constexpr bool FWD = MODE != G_REV;
     constexpr bool AGG = REV && K != 0;
+    static_assert(AGG == (S > 0), "a table exactly when the reverse scatters a fused gather");
     constexpr int NL = NS < kGLeaves ? NS : kGLeaves;
     __shared__ double lds[BS / kWave];
-    __shared__ typename std::conditional<AGG, AggTable, int>::type tab;
+    __shared__ typename std::conditional<AGG, AggTableT<S>, int>::type tab;
     const bool scatter = AGG && g.gsrc_shadow != nullptr;
     const int64_t i = xcd_remap(blockIdx.x, gridDim.x) * BS + threadIdx.x;
     const bool ok = i < g.n;
@@ -401,12 +403,24 @@ __global__ void __launch_bounds__(BS) k_group(GroupDev g) {
 template <int K, int NS>
 hipError_t launch_group_k(const GroupDev& g, int mode, hipStream_t s) {
     constexpr int BS = kGroupBlock, BSS = K != 0 ? kGroupBlockScatter : kGroupBlock;
+    constexpr int SB = K != 0 ? kAggSlots : 0, SS = K != 0 ? kAggSlotsSmall : 0;
     const dim3 grid((unsigned)group_blocks(g.n, BS)), block(BS);
     const dim3 grid_s((unsigned)group_blocks(g.n, BSS)), block_s(BSS);
+    const bool small = g.agg_slots == kAggSlotsSmall;
     switch (mode) {
-        case G_FWD: PG_LAUNCH((k_group<K, G_FWD, BS, NS>), grid, block, 0, s, g); break;
-        case G_REV: PG_LAUNCH((k_group<K, G_REV, BSS, NS>), grid_s, block_s, 0, s, g); break;
-        default: PG_LAUNCH((k_group<K, G_FWDREV, BSS, NS>), grid_s, block_s, 0, s, g); break;
+        case G_FWD: PG_LAUNCH((k_group<K, G_FWD, BS, NS, 0>), grid, block, 0, s, g); break;
+        case G_REV:
+            if (small)
+                PG_LAUNCH((k_group<K, G_REV, BSS, NS, SS>), grid_s, block_s, 0, s, g);
+            else
+                PG_LAUNCH((k_group<K, G_REV, BSS, NS, SB>), grid_s, block_s, 0, s, g);
+            break;
+        default:
+            if (small)
+                PG_LAUNCH((k_group<K, G_FWDREV, BSS, NS, SS>), grid_s, block_s, 0, s, g);
+            else
+                PG_LAUNCH((k_group<K, G_FWDREV, BSS, NS, SB>), grid_s, block_s, 0, s, g);
+            break;
     }
     return hipGetLastError();
 }
