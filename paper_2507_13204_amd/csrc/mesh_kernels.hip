@@ -141,10 +141,20 @@ k_segmented_sum(const double* __restrict__ partials, const int64_t* __restrict__
     if (threadIdx.x == 0) out[i] = s;
 }
 
-__global__ void __launch_bounds__(256) k_zero16(uint4* __restrict__ p, int64_t n16) {
+// Zeroes bytes [0, head + 16 n16 + tail) of p, where p + head is 16-byte
+// aligned and head, tail < 16: 16-byte stores over the aligned middle, single
+// bytes at the two ends (workgroup 0).
+__global__ void __launch_bounds__(256)
+k_zero16(uint8_t* __restrict__ p, int64_t head, int64_t n16, int64_t tail) {
+    uint4* __restrict__ mid = reinterpret_cast<uint4*>(p + head);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
-        p[i] = make_uint4(0u, 0u, 0u, 0u);
+        mid[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (blockIdx.x == 0) {
+        const int t = (int)threadIdx.x;
+        if (t < head) p[t] = 0;
+        if (t < tail) p[head + 16 * n16 + t] = 0;
+    }
 }
 
 __global__ void __launch_bounds__(256) k_zero1(uint8_t* __restrict__ p, int64_t n) {
@@ -434,14 +444,10 @@ hipError_t launch_segmented_sum(const double* partials, const int64_t* seg, int6
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
     if (bytes == 0) return hipSuccess;
     const uintptr_t a = reinterpret_cast<uintptr_t>(p);
-    if ((a % 16) == 0 && (bytes % 16) == 0) {
-        const int64_t n16 = (int64_t)(bytes / 16);
-        hipLaunchKernelGGL(k_zero16, dim3(stream_grid(n16, 256, 1 << 20)), dim3(256), 0, s,
-                           (uint4*)p, n16);
-    } else {
-        hipLaunchKernelGGL(k_zero1, dim3((unsigned)((bytes + 255) / 256)), dim3(256), 0, s,
-                           (uint8_t*)p, (int64_t)bytes);
-    }
+    const int64_t head = std::min<int64_t>((int64_t)((16 - a % 16) % 16), (int64_t)bytes);
+    const int64_t n16 = ((int64_t)bytes - head) / 16, tail = (int64_t)bytes - head - 16 * n16;
+    hipLaunchKernelGGL(k_zero16, dim3(stream_grid(n16, 256, 1 << 20)), dim3(256), 0, s,
+                       (uint8_t*)p, head, n16, tail);
     return hipGetLastError();
 }
 

@@ -104,6 +104,24 @@ def test_accumulate_adds_into_grad():
         assert rel(g.cpu().numpy(), base.cpu().numpy() + g_ref) <= TOL_F64_G
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("offset", [0, 1, 3])
+def test_gradient_into_an_offset_view(dtype, offset):
+    """grad starting 4 or 8 bytes past a 16-byte boundary, with an odd node
+    count: the gradient's fill covers the unaligned head and tail exactly, and
+    the guard entries on both sides stay untouched."""
+    m = inputs.random_mesh(1001, 2003, 4, 31)
+    obj, x = _obj(m, dtype)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    buf = torch.full((m.n_nodes + offset + 5,), 7.0, dtype=tdt, device="cuda")
+    g = buf[offset:offset + m.n_nodes]
+    g.fill_(float("nan"))
+    f, _ = obj.gradient(x, out=g)
+    _check(m, f.item(), g.cpu().numpy(), dtype)
+    host = buf.cpu().numpy()
+    assert (host[:offset] == 7.0).all() and (host[offset + m.n_nodes:] == 7.0).all()
+
+
 @pytest.mark.parametrize("adj", ["gather", "colour", "tiled"])
 def test_deterministic_variants_are_bitwise_repeatable(adj):
     m = inputs.hex_mesh(31, seed=14)
