@@ -79,6 +79,25 @@ def test_mesh_gradient_parity_f32(name, adj):
     _check(m, f.item(), g.cpu().numpy(), "f32")
 
 
+@pytest.mark.parametrize("name", ["hex23", "rand_k8"])
+def test_f32_error_against_the_f64_input_oracle(name):
+    """FP32 storage is gated against the oracle on the FP32-rounded inputs;
+    against the oracle on the original FP64 inputs the error is that of
+    rounding x, B and w to FP32 (a few units of 2^-24 times the problem's
+    conditioning), reported here and bounded loosely."""
+    m = MESHES[name]()
+    obj, x = _obj(m, "f32")
+    f, g = obj.gradient(x)
+    g = g.cpu().numpy().astype(np.float64)
+    f_r, g_r = _oracle_grad(m, "f32")
+    f_64, g_64 = _oracle_grad(m, "f64")
+    e_r, e_64 = rel(g, g_r), rel(g, g_64)
+    print(f"{name}: FP32 gradient error vs rounded-input oracle {e_r:.2e}, "
+          f"vs FP64-input oracle {e_64:.2e}; f {srel(f.item(), f_r):.2e} / {srel(f.item(), f_64):.2e}")
+    assert e_r <= TOL_F32 and srel(f.item(), f_r) <= TOL_F32
+    assert e_64 <= 1e-4 and srel(f.item(), f_64) <= 1e-4
+
+
 @pytest.mark.parametrize("adj,ckpt", VARIANTS)
 def test_adjoint_seed_and_tape(adj, ckpt):
     m = inputs.hex_mesh(15, seed=12)
