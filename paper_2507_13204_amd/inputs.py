@@ -21,6 +21,11 @@ up to 10,000 entries; the element form below generalises it):
                            W m x n ~ U(0.5,1.5)                               (seed 3)
 * ``uneven_batch(k)``   -- k hex meshes with side s = round(10**(1+U)),
                            U ~ U[0,1), concatenated                           (seed 4)
+* ``ring_mesh(E, k)``   -- E elements on a ring of E nodes, element e on nodes
+                           e, e+1, ..., e+k-1 (mod E): the largest incidence
+                           count the int32 index range admits is E k < 2^31
+* ``wide_index_mesh``   -- few elements on nodes at both ends of [0, 2^31 - 1),
+                           x nonzero only on the nodes they touch
 """
 from __future__ import annotations
 
@@ -118,6 +123,53 @@ def random_mesh(n_nodes: int, n_elems: int, k: int, seed: int) -> Mesh:
     B = rng.standard_normal((n_elems, k))
     w = rng.uniform(0.5, 1.5, n_elems)
     return Mesh(n_nodes, n_elems, k, conn, B, w, x, f"rand{n_nodes}x{n_elems}x{k}")
+
+
+def ring_mesh(n_elems: int, k: int, seed: int = 7) -> Mesh:
+    """E elements on a ring of E nodes, conn[e, j] = (e + j) mod E; B ~ N(0,1),
+    w ~ U(0.5,1.5), x ~ U(-1,1) (drawn x, B, w).  Built in int32 without a
+    64-bit intermediate so that E k close to 2^31 fits in host memory."""
+    rng = np.random.default_rng(seed)
+    E = n_elems
+    conn = np.add.outer(np.arange(E, dtype=np.int32), np.arange(k, dtype=np.int32))
+    conn[conn >= E] -= E
+    x = rng.uniform(-1.0, 1.0, E)
+    B = rng.standard_normal((E, k))
+    w = rng.uniform(0.5, 1.5, E)
+    return Mesh(E, E, k, conn, B, w, x, f"ring{E}x{k}")
+
+
+@dataclasses.dataclass
+class WideIndexMesh:
+    """A mesh over n_nodes nodes whose x is zero except on the nodes the
+    elements touch (x_nodes, ascending, with values x_vals)."""
+
+    n_nodes: int
+    n_elems: int
+    k: int
+    conn: np.ndarray
+    B: np.ndarray
+    w: np.ndarray
+    x_nodes: np.ndarray  # int64, ascending
+    x_vals: np.ndarray   # float64
+
+
+def wide_index_mesh(n_nodes: int, n_elems: int, k: int, span: int, seed: int = 8) -> WideIndexMesh:
+    """Connectivity uniform over [0, span) and [n_nodes - span, n_nodes) (half
+    the incidences each, the last node always present), B ~ N(0,1),
+    w ~ U(0.5,1.5), x ~ U(-1,1) on the touched nodes (drawn in this order:
+    conn, B, w, x)."""
+    rng = np.random.default_rng(seed)
+    low = rng.integers(0, span, size=(n_elems, k))
+    high = rng.integers(n_nodes - span, n_nodes, size=(n_elems, k))
+    conn = np.where(rng.random((n_elems, k)) < 0.5, low, high)
+    conn[-1, -1] = n_nodes - 1
+    conn = conn.astype(np.int32)
+    B = rng.standard_normal((n_elems, k))
+    w = rng.uniform(0.5, 1.5, n_elems)
+    nodes = np.unique(conn.astype(np.int64))
+    x = rng.uniform(-1.0, 1.0, nodes.size)
+    return WideIndexMesh(n_nodes, n_elems, k, conn, B, w, nodes, x)
 
 
 @dataclasses.dataclass
