@@ -1133,9 +1133,12 @@ pg_status pg_bind_workspace(pg_plan p, void* workspace, size_t bytes, pg_stream 
     switch (p->kind) {
         case K_MESH: st = mesh_bind(p, s); break;
         case K_BATCH: st = batch_bind(p, s); break;
+        case K_LAPLACE:
+            PG_HIP(launch_zero(p->at<int32_t>(p->o_flag), sizeof(int32_t) * 4, s));
+            PG_HIP(hipStreamSynchronize(s));
+            break;
         case K_DENSE:
-        case K_BDENSE:
-        case K_LAPLACE: break;
+        case K_BDENSE: break;
     }
     if (st == PG_OK) p->bound = true;
     return st;
@@ -1246,6 +1249,7 @@ pg_status pg_laplace1d_plan(pg_plan* plan, int64_t n, pg_dtype dtype, const pg_o
     Layout L;
     p->n_partials = (size_t)std::max<int64_t>(laplace1d_blocks(n), 1);
     p->o_partials = L.take(sizeof(double) * p->n_partials);
+    p->o_flag = L.take(sizeof(int32_t) * 4);  // the fused final sum's ticket
     if (p->lap_atomic && dtype == PG_F32) p->o_gacc = L.take(sizeof(double) * (size_t)n);
     p->ws_bytes = L.total;
     *workspace_bytes = p->ws_bytes;
@@ -1276,10 +1280,13 @@ pg_status pg_laplace1d_objective(pg_plan p, const void* x, const void* b, double
     double* partials = p->at<double>(p->o_partials);
     const Dtype dt = p->dtype == PG_F64 ? F64 : F32;
     PG_HIP(tmark(p, 2, true, s));
+    int32_t* ticket = p->at<int32_t>(p->o_flag);
+    const bool fused = laplace1d_fused(p->lap_n);
     PG_HIP(tkern(p, true));
-    PG_HIP(launch_laplace1d(p->lap_n, dt, 0, x, b, nullptr, nullptr, nullptr, nullptr, partials, 0, s));
+    PG_HIP(launch_laplace1d(p->lap_n, dt, 0, x, b, nullptr, nullptr, nullptr, nullptr, partials, 0,
+                            ticket, f_out, s));
     PG_HIP(tkern(p, false));
-    PG_HIP(launch_final_sum(partials, laplace1d_blocks(p->lap_n), f_out, s));
+    if (!fused) PG_HIP(launch_final_sum(partials, laplace1d_blocks(p->lap_n), f_out, s));
     PG_HIP(tmark(p, 2, false, s));
     return PG_OK;
 }
@@ -1303,6 +1310,8 @@ pg_status pg_laplace1d_gradient(pg_plan p, const void* x, const void* b, void* g
     double* partials = p->at<double>(p->o_partials);
     const Dtype dt = p->dtype == PG_F64 ? F64 : F32;
     const int acc = p->opt.accumulate;
+    int32_t* ticket = p->at<int32_t>(p->o_flag);
+    const bool fused = laplace1d_fused(p->lap_n);
     PG_HIP(tmark(p, 2, true, s));
     if (p->lap_atomic) {
         double* g64 = nullptr;
@@ -1311,15 +1320,17 @@ pg_status pg_laplace1d_gradient(pg_plan p, const void* x, const void* b, void* g
             if (dt == F32 || !acc) PG_HIP(launch_zero(g64, sizeof(double) * (size_t)p->lap_n, s));
         }
         PG_HIP(tkern(p, true));
-        PG_HIP(launch_laplace1d(p->lap_n, dt, 2, x, b, g64, nullptr, gb, nullptr, partials, acc, s));
+        PG_HIP(launch_laplace1d(p->lap_n, dt, 2, x, b, g64, nullptr, gb, nullptr, partials, acc,
+                                ticket, f_out, s));
         PG_HIP(tkern(p, false));
         if (gx && dt == F32) PG_HIP(launch_f64_to_f32(g64, static_cast<float*>(gx), p->lap_n, acc, s));
     } else {
         PG_HIP(tkern(p, true));
-        PG_HIP(launch_laplace1d(p->lap_n, dt, 1, x, b, nullptr, gx, gb, nullptr, partials, acc, s));
+        PG_HIP(launch_laplace1d(p->lap_n, dt, 1, x, b, nullptr, gx, gb, nullptr, partials, acc,
+                                ticket, f_out, s));
         PG_HIP(tkern(p, false));
     }
-    if (f_out) PG_HIP(launch_final_sum(partials, laplace1d_blocks(p->lap_n), f_out, s));
+    if (f_out && !fused) PG_HIP(launch_final_sum(partials, laplace1d_blocks(p->lap_n), f_out, s));
     PG_HIP(tmark(p, 2, false, s));
     return PG_OK;
 }

@@ -245,10 +245,14 @@ namespace pg {
 // mode 0: objective; 1: gradient (gather form, writes gx / gb of dtype);
 // 2: gradient (atomic form: FP64 atomics into gx64, which must be zeroed
 // or hold the values to add to; gb of dtype).  partials: one per 256 nodes.
+// When laplace1d_fused(n) the launch also writes f to f_out (if not null)
+// through the zero-initialised ticket; otherwise the caller sums the partials.
 int64_t laplace1d_blocks(int64_t n);
+bool laplace1d_fused(int64_t n);
 hipError_t launch_laplace1d(int64_t n, Dtype dt, int mode, const void* x, const void* b,
                             double* gx64, void* gx, void* gb, const double* fbar,
-                            double* partials, int accumulate, hipStream_t s);
+                            double* partials, int accumulate, int32_t* ticket, double* f_out,
+                            hipStream_t s);
 
 }  // namespace pg
 
