@@ -178,7 +178,8 @@ struct pg_plan_s {
     size_t o_partials = NONE, o_flag = NONE, o_u = NONE, o_v = NONE, o_offs = NONE,
            o_cursor = NONE, o_inc = NONE, o_scan = NONE, o_gacc = NONE, o_colpart = NONE,
            o_tiles = NONE, o_vmat = NONE, o_tbase = NONE, o_loff = NONE, o_lidx = NONE,
-           o_stage = NONE, o_noff = NONE, o_npos = NONE;
+           o_stage = NONE, o_noff = NONE, o_npos = NONE, o_small = NONE, o_ticket = NONE;
+    bool small = false;       // each call one launch (small_kernels.hip)
     int tiled_tile = 0;       // elements per tile of the two-level deterministic adjoint
     int64_t tiled_nt = 0;
     size_t n_partials = 0;
@@ -227,6 +228,8 @@ pg_status check_opts(const pg_options* o, pg_options* out) {
         return fail(PG_EINVAL, "options.accumulate must be 0 or 1");
     if (out->scatter < 0 || out->scatter > 3)
         return fail(PG_EINVAL, "options.scatter must be 0, 1, 2 or 3");
+    if (out->onepass != 0 && out->onepass != 1)
+        return fail(PG_EINVAL, "options.onepass must be 0 or 1");
     return PG_OK;
 }
 
@@ -257,6 +260,14 @@ void layout_mesh(pg_plan_s* p) {
     p->opt.tile = ept;
     p->mesh_blocks_n = mesh_blocks(m.n_elems, p->opt.block, ept);
     p->n_partials = (size_t)std::max<int64_t>(p->mesh_blocks_n, 1);
+    p->small = p->opt.onepass == 0 && p->opt.adjoint == PG_ADJ_ATOMIC &&
+               mesh_small_eligible(m, p->opt.block);
+    if (p->small) {
+        // one element per thread: the grid can exceed the tiled pass's
+        p->n_partials = std::max<size_t>(p->n_partials, (size_t)mesh_blocks(m.n_elems, p->opt.block, 1));
+        p->o_small = L.take(sizeof(double) * (size_t)m.n_nodes);
+        p->o_ticket = L.take(sizeof(int32_t) * 4);
+    }
     p->o_partials = L.take(sizeof(double) * p->n_partials);
     p->o_flag = L.take(sizeof(int32_t) * 4);
     if (p->opt.ckpt == PG_STORE) p->o_u = L.take(sizeof(double) * (size_t)m.n_elems);
@@ -486,6 +497,35 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
     const bool acc = p->opt.accumulate != 0;
     const bool obj = (want & W_OBJ) != 0;
     const bool grd = (want & W_GRAD) != 0;
+    if (p->small) {
+        // One launch: the element work, the scatter into the zeroed buffer,
+        // and (last workgroup) grad from the buffer, the buffer cleared, f.
+        SmallPass sp;
+        sp.ticket = p->at<int32_t>(p->o_ticket);
+        sp.accumulate = acc;
+        sp.f_out = obj ? f_out : nullptr;
+        MeshMode mode = M_PRIMAL;
+        if (!grd) {
+            q.u_store = p->at<double>(p->o_u);
+        } else {
+            q.fbar = fbar;
+            if (!obj && p->opt.ckpt == PG_STORE) {
+                if (!p->tape_valid) return fail(PG_ESTATE, "no stored forward values: call pg_objective first");
+                q.u_in = p->at<double>(p->o_u);
+            }
+            q.gacc = p->at<double>(p->o_small);
+            sp.grad = grad;
+            mode = obj ? M_GRAD_ATOMIC : M_ADJ_ATOMIC;
+        }
+        PG_HIP(tkern(p, true));
+        PG_HIP(launch_mesh_small(m, mode, q, sp, s));
+        PG_HIP(tkern(p, false));
+        if (!grd && q.u_store) {
+            p->tape_valid = true;
+            p->tape_x = x;
+        }
+        return PG_OK;
+    }
     if (!grd) {
         q.u_store = p->at<double>(p->o_u);
         PG_HIP(tkern(p, true));
@@ -736,6 +776,11 @@ pg_status mesh_bind(pg_plan p, hipStream_t s) {
     PG_HIP(hipMemcpyAsync(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
     if (hflag) return fail(PG_ERANGE, "connectivity has an entry outside [0, %lld)", (long long)m.n_nodes);
+    if (p->small) {  // zero between calls from here on
+        PG_HIP(launch_zero(p->at<double>(p->o_small), sizeof(double) * (size_t)m.n_nodes, s));
+        PG_HIP(launch_zero(p->at<int32_t>(p->o_ticket), sizeof(int32_t) * 4, s));
+        PG_HIP(hipStreamSynchronize(s));
+    }
     if (p->opt.scatter != 1 && m.n_elems > 0) {
         std::vector<std::vector<int32_t>> tiles;
         pg_status hst = sample_mesh_tiles(m.conn, m.n_elems, m.k, 0,
@@ -974,6 +1019,7 @@ pg_options pg_default_options(void) {
     o.tile = 0;
     o.accumulate = 0;
     o.scatter = 0;
+    o.onepass = 0;
     return o;
 }
 

@@ -82,6 +82,22 @@ struct MeshPass {
 // Number of workgroups an element pass over n items launches.
 int64_t mesh_blocks(int64_t n_items, int block, int ept);
 
+// One launch per call for small single meshes (small_kernels.hip): the
+// scatter gathers in p.gacc (FP64, n_nodes entries, zero between calls) and
+// the last workgroup writes grad, clears p.gacc and writes f.
+struct SmallPass {
+    int32_t* ticket = nullptr;  // zero between calls; the last workgroup re-arms it
+    void* grad = nullptr;       // gradient output (dtype), gradient modes
+    double* f_out = nullptr;    // f, objective modes (may be null)
+    int accumulate = 0;         // add into grad instead of overwriting it
+};
+constexpr int64_t kSmallMaxBlocks = 64;
+constexpr int64_t kSmallMaxNodes = 16384;
+bool mesh_small_eligible(const MeshView& m, int block);
+// mode: M_PRIMAL, M_GRAD_ATOMIC or M_ADJ_ATOMIC.
+hipError_t launch_mesh_small(const MeshView& m, MeshMode mode, const MeshPass& p,
+                             const SmallPass& sp, hipStream_t s);
+
 // Plan-time structures of the two-level deterministic adjoint (tiled_kernels.hip):
 // tile t = elements [t * tile, (t + 1) * tile); its local nodes are the
 // distinct nodes it touches, in ascending order, with staging slots

@@ -62,7 +62,7 @@ class ProgStats(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("adjoint", ctypes.c_int32), ("ckpt", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("accumulate", ctypes.c_int32),
-                ("scatter", ctypes.c_int32)]
+                ("scatter", ctypes.c_int32), ("onepass", ctypes.c_int32)]
 
 
 class Instance(ctypes.Structure):
@@ -151,7 +151,7 @@ def check(code: int, where: str):
 
 
 def make_options(adjoint="auto", ckpt="recompute", block: int = 0, tile: int = 0,
-                 accumulate: bool = False, scatter: int = 0) -> Options:
+                 accumulate: bool = False, scatter: int = 0, onepass: bool = True) -> Options:
     o = Options()
     o.adjoint = ADJOINTS[adjoint] if isinstance(adjoint, str) else int(adjoint)
     o.ckpt = CKPTS[ckpt] if isinstance(ckpt, str) else int(ckpt)
@@ -159,6 +159,7 @@ def make_options(adjoint="auto", ckpt="recompute", block: int = 0, tile: int = 0
     o.tile = int(tile)
     o.accumulate = int(bool(accumulate))
     o.scatter = int(scatter)
+    o.onepass = 0 if onepass else 1
     return o
 
 
@@ -254,7 +255,7 @@ class MeshObjective(_Plan):
 
     def __init__(self, conn: torch.Tensor, B: torch.Tensor, w: torch.Tensor, n_nodes: int,
                  adjoint="auto", ckpt="recompute", block: int = 0, tile: int = 0,
-                 accumulate: bool = False, scatter: int = 0, stream=None):
+                 accumulate: bool = False, scatter: int = 0, onepass: bool = True, stream=None):
         super().__init__()
         _need_cuda(conn, B, w)
         if conn.dtype != torch.int32:
@@ -264,7 +265,7 @@ class MeshObjective(_Plan):
         self.conn, self.B, self.w = conn, B, w
         self.n_nodes, self.n_elems, self.k = int(n_nodes), int(E), int(k)
         self.dtype = B.dtype
-        self.options = make_options(adjoint, ckpt, block, tile, accumulate, scatter)
+        self.options = make_options(adjoint, ckpt, block, tile, accumulate, scatter, onepass)
         sz = ctypes.c_size_t()
         check(lib().pg_mesh_plan(ctypes.byref(self._plan), self.n_nodes, E, k, _ptr(conn),
                                  _ptr(B), _ptr(w), _dtype_code(B), ctypes.byref(self.options),

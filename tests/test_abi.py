@@ -85,6 +85,7 @@ def test_mesh_plan_is_host_only_and_sizes_workspace():
     (dict(opts="bad_block"), P.EINVAL),
     (dict(opts="bad_tile"), P.EINVAL),
     (dict(opts="bad_scatter"), P.EINVAL),
+    (dict(opts="bad_onepass"), P.EINVAL),
 ])
 def test_mesh_plan_argument_errors(kw, code):
     if kw.get("opts") == "bad_adjoint":
@@ -95,10 +96,39 @@ def test_mesh_plan_argument_errors(kw, code):
         kw["opts"] = P.make_options(tile=3)
     elif kw.get("opts") == "bad_scatter":
         kw["opts"] = P.make_options(scatter=4)
+    elif kw.get("opts") == "bad_onepass":
+        kw["opts"] = P.make_options()
+        kw["opts"].onepass = 2
     st, plan, _ = plan_mesh(**kw)
     assert st == code
     assert not plan.value
     assert len(P.lib().pg_last_error()) > 0
+
+
+@pytest.mark.parametrize("n_nodes,n_elems,k,adjoint,small", [
+    (2000, 1000, 8, "atomic", True),        # 2 workgroups of 512, 2,000 nodes
+    (10_000, 9_999, 2, "atomic", True),     # the 1D chain of 10^4 nodes
+    (16_384, 32_768, 4, "atomic", True),    # 64 workgroups and 16,384 nodes: the limits
+    (16_385, 1000, 8, "atomic", False),     # one node too many
+    (2000, 32_769, 8, "atomic", False),     # 65 workgroups
+    (2000, 1000, 5, "atomic", False),       # k not held in registers
+    (2000, 1000, 8, "gather", False),       # not the atomic adjoint
+])
+def test_one_launch_plans_take_a_node_buffer(n_nodes, n_elems, k, adjoint, small):
+    """A small mesh's plan (atomic adjoint, k = 2, 4 or 8, at most 64
+    workgroups and 16,384 nodes) holds an FP64 buffer of n_nodes entries and a
+    ticket for its one-launch calls; onepass = 1 or any larger mesh does not."""
+    st, plan, ws = plan_mesh(n_nodes=n_nodes, n_elems=n_elems, k=k,
+                             opts=P.make_options(adjoint=adjoint))
+    st2, plan2, ws_off = plan_mesh(n_nodes=n_nodes, n_elems=n_elems, k=k,
+                                   opts=P.make_options(adjoint=adjoint, onepass=False))
+    assert st == P.OK and st2 == P.OK
+    if small:
+        assert ws - ws_off >= 8 * n_nodes
+    else:
+        assert ws == ws_off
+    P.lib().pg_plan_destroy(plan)
+    P.lib().pg_plan_destroy(plan2)
 
 
 def test_empty_mesh_plan_is_valid():

@@ -328,3 +328,35 @@ def test_tiled_adjoint_tile_sizes(name, block):
     g2 = g.clone()
     acc.gradient(x, out=g2)
     assert rel(g2.cpu().numpy(), 2.0 * g.cpu().numpy()) <= 1e-15
+
+
+@pytest.mark.parametrize("name", ["chain10k", "hex17", "hex23", "rand_k8", "rand_k4"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_one_launch_small_meshes(name, dtype):
+    """Small meshes run each call as one launch (scatter into a zeroed buffer,
+    the last workgroup writes grad, clears the buffer and sums f).  Against
+    the oracle and the multi-launch path, over repeated calls (the buffer and
+    the ticket must be clear again after each), the seeded adjoint, the stored
+    forward values and accumulation."""
+    m = MESHES[name]()
+    one, x = _obj(m, dtype)
+    multi, _ = _obj(m, dtype, onepass=False)
+    tol_g = TOL_F64_G if dtype == "f64" else TOL_F32
+    for _ in range(3):
+        f, g = one.gradient(x)
+        _check(m, f.item(), g.cpu().numpy(), dtype)
+        assert srel(one.objective(x).item(), f.item()) <= 1e-15
+    f2, g2 = multi.gradient(x)
+    assert srel(f.item(), f2.item()) <= 1e-14
+    assert rel(g.cpu().numpy(), g2.cpu().numpy()) <= tol_g
+    fbar = torch.tensor([0.75], dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        _check(m, None, one.adjoint(x, fbar).cpu().numpy(), dtype, fbar=0.75)
+    st, _ = _obj(m, dtype, ckpt="store")
+    st.objective(x)
+    _check(m, None, st.adjoint(x, fbar).cpu().numpy(), dtype, fbar=0.75)
+    acc, _ = _obj(m, dtype, accumulate=True)
+    base = g.clone()
+    acc.gradient(x, out=base)
+    acc.gradient(x, out=base)
+    assert rel(base.cpu().numpy().astype(np.float64), 3.0 * g.cpu().numpy().astype(np.float64)) <= tol_g
