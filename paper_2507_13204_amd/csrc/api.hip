@@ -178,7 +178,8 @@ struct pg_plan_s {
     size_t o_partials = NONE, o_flag = NONE, o_u = NONE, o_v = NONE, o_offs = NONE,
            o_cursor = NONE, o_inc = NONE, o_scan = NONE, o_gacc = NONE, o_colpart = NONE,
            o_tiles = NONE, o_vmat = NONE, o_tbase = NONE, o_loff = NONE, o_lidx = NONE,
-           o_stage = NONE, o_noff = NONE, o_npos = NONE, o_small = NONE, o_ticket = NONE;
+           o_stage = NONE, o_noff = NONE, o_npos = NONE, o_small = NONE, o_ticket = NONE,
+           o_small_meta = NONE;
     bool small = false;       // each call one launch (small_kernels.hip)
     int tiled_tile = 0;       // elements per tile of the two-level deterministic adjoint
     int64_t tiled_nt = 0;
@@ -204,6 +205,13 @@ namespace {
 // element pass on a 128^3 hex mesh (four element rows per workgroup share
 // their node rows in the LDS table); it is also the default elsewhere.
 constexpr int kDefaultBlock = 512;
+
+// Layout of the one-launch path's range tables (int32): range_done and
+// range_need (kSmallMaxRanges each), wg_off (kSmallMaxBlocks + 1), wg_list
+// (at most kSmallMaxRanges per workgroup).
+constexpr int64_t small_meta_ints() {
+    return 2 * kSmallMaxRanges + (kSmallMaxBlocks + 1) + kSmallMaxBlocks * kSmallMaxRanges;
+}
 
 // Entries per tile of the int16 local-node offsets: at most tile * k + 1 are
 // used; the rest pads every tile to whole 16-byte chunks.
@@ -267,6 +275,8 @@ void layout_mesh(pg_plan_s* p) {
         p->n_partials = std::max<size_t>(p->n_partials, (size_t)mesh_blocks(m.n_elems, p->opt.block, 1));
         p->o_small = L.take(sizeof(double) * (size_t)m.n_nodes);
         p->o_ticket = L.take(sizeof(int32_t) * 4);
+        // range_done, range_need, wg_off, wg_list
+        p->o_small_meta = L.take(sizeof(int32_t) * (size_t)small_meta_ints());
     }
     p->o_partials = L.take(sizeof(double) * p->n_partials);
     p->o_flag = L.take(sizeof(int32_t) * 4);
@@ -501,7 +511,12 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
         // One launch: the element work, the scatter into the zeroed buffer,
         // and (last workgroup) grad from the buffer, the buffer cleared, f.
         SmallPass sp;
+        int32_t* meta = p->at<int32_t>(p->o_small_meta);
         sp.ticket = p->at<int32_t>(p->o_ticket);
+        sp.range_done = meta;
+        sp.range_need = meta + kSmallMaxRanges;
+        sp.wg_off = meta + 2 * kSmallMaxRanges;
+        sp.wg_list = sp.wg_off + (kSmallMaxBlocks + 1);
         sp.accumulate = acc;
         sp.f_out = obj ? f_out : nullptr;
         MeshMode mode = M_PRIMAL;
@@ -760,6 +775,50 @@ pg_status mesh_colour(pg_plan p, hipStream_t s) {
     return PG_OK;
 }
 
+// Range tables of the one-launch path (host, at bind): the node ranges each
+// workgroup's elements touch, how many workgroups count on each range, and
+// every untouched range given to workgroup 0 so that it is written too.  The
+// node buffer, the counts and the ticket start at zero.
+pg_status mesh_small_build(pg_plan p, hipStream_t s) {
+    const MeshView& m = p->mesh;
+    const int64_t G = mesh_blocks(m.n_elems, p->opt.block, 1);
+    const int R = (int)((m.n_nodes + kSmallRange - 1) / kSmallRange);
+    std::vector<int32_t> conn((size_t)(m.n_elems * m.k));
+    PG_HIP(hipMemcpyAsync(conn.data(), m.conn, sizeof(int32_t) * conn.size(), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> meta((size_t)small_meta_ints(), 0);
+    int32_t* need = meta.data() + kSmallMaxRanges;
+    int32_t* wg_off = need + kSmallMaxRanges;
+    int32_t* wg_list = wg_off + (kSmallMaxBlocks + 1);
+    std::vector<char> touched((size_t)R);
+    int32_t pos = 0;
+    for (int64_t w = 0; w < G; ++w) {
+        std::fill(touched.begin(), touched.end(), 0);
+        const int64_t e0 = w * p->opt.block, e1 = std::min(m.n_elems, e0 + p->opt.block);
+        for (int64_t q = e0 * m.k; q < e1 * m.k; ++q) touched[(size_t)(conn[(size_t)q] / kSmallRange)] = 1;
+        if (w == 0) {
+            // ranges no workgroup touches are counted on by workgroup 0
+            std::vector<char> any((size_t)R, 0);
+            for (int32_t c : conn) any[(size_t)(c / kSmallRange)] = 1;
+            for (int r = 0; r < R; ++r)
+                if (!any[(size_t)r]) touched[(size_t)r] = 1;
+        }
+        wg_off[w] = pos;
+        for (int r = 0; r < R; ++r)
+            if (touched[(size_t)r]) {
+                wg_list[pos++] = r;
+                need[r]++;
+            }
+    }
+    wg_off[G] = pos;
+    PG_HIP(hipMemcpyAsync(p->at<int32_t>(p->o_small_meta), meta.data(), sizeof(int32_t) * meta.size(),
+                          hipMemcpyHostToDevice, s));
+    PG_HIP(launch_zero(p->at<double>(p->o_small), sizeof(double) * (size_t)m.n_nodes, s));
+    PG_HIP(launch_zero(p->at<int32_t>(p->o_ticket), sizeof(int32_t) * 4, s));
+    PG_HIP(hipStreamSynchronize(s));
+    return PG_OK;
+}
+
 pg_status mesh_bind(pg_plan p, hipStream_t s) {
     const MeshView& m = p->mesh;
     int32_t* flag = p->at<int32_t>(p->o_flag);
@@ -776,10 +835,9 @@ pg_status mesh_bind(pg_plan p, hipStream_t s) {
     PG_HIP(hipMemcpyAsync(&hflag, flag, sizeof hflag, hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
     if (hflag) return fail(PG_ERANGE, "connectivity has an entry outside [0, %lld)", (long long)m.n_nodes);
-    if (p->small) {  // zero between calls from here on
-        PG_HIP(launch_zero(p->at<double>(p->o_small), sizeof(double) * (size_t)m.n_nodes, s));
-        PG_HIP(launch_zero(p->at<int32_t>(p->o_ticket), sizeof(int32_t) * 4, s));
-        PG_HIP(hipStreamSynchronize(s));
+    if (p->small) {
+        pg_status sst = mesh_small_build(p, s);
+        if (sst != PG_OK) return sst;
     }
     if (p->opt.scatter != 1 && m.n_elems > 0) {
         std::vector<std::vector<int32_t>> tiles;

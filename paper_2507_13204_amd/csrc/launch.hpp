@@ -82,17 +82,27 @@ struct MeshPass {
 // Number of workgroups an element pass over n items launches.
 int64_t mesh_blocks(int64_t n_items, int block, int ept);
 
-// One launch per call for small single meshes (small_kernels.hip): the
-// scatter gathers in p.gacc (FP64, n_nodes entries, zero between calls) and
-// the last workgroup writes grad, clears p.gacc and writes f.
+// One launch per call for small single meshes (small_kernels.hip).  The
+// scatter gathers in p.gacc (FP64, n_nodes entries, zero between calls).
+// Nodes are split in ranges of kSmallRange; a workgroup that has scattered
+// counts itself done on every range its elements touch (plus, for workgroup
+// 0, every range no element touches), and the last workgroup done on a range
+// writes grad there from p.gacc and clears p.gacc there.  The last workgroup
+// to take the ticket sums the partials into f.
 struct SmallPass {
-    int32_t* ticket = nullptr;  // zero between calls; the last workgroup re-arms it
+    int32_t* ticket = nullptr;           // f's ticket, zero between calls
+    int32_t* range_done = nullptr;       // per range, zero between calls
+    const int32_t* range_need = nullptr; // per range: workgroups that count on it (>= 1)
+    const int32_t* wg_off = nullptr;     // workgroup w's ranges: wg_list[wg_off[w] .. wg_off[w+1])
+    const int32_t* wg_list = nullptr;
     void* grad = nullptr;       // gradient output (dtype), gradient modes
     double* f_out = nullptr;    // f, objective modes (may be null)
     int accumulate = 0;         // add into grad instead of overwriting it
 };
 constexpr int64_t kSmallMaxBlocks = 64;
 constexpr int64_t kSmallMaxNodes = 16384;
+constexpr int kSmallRange = 512;
+constexpr int kSmallMaxRanges = (int)(kSmallMaxNodes / kSmallRange);
 bool mesh_small_eligible(const MeshView& m, int block);
 // mode: M_PRIMAL, M_GRAD_ATOMIC or M_ADJ_ATOMIC.
 hipError_t launch_mesh_small(const MeshView& m, MeshMode mode, const MeshPass& p,

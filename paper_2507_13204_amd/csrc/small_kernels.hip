@@ -5,12 +5,14 @@
 // final sum).  Here one launch does it all: the element work is the same as
 // the element pass (rows, gather, psi, the LDS-combined atomic scatter), but
 // the contributions go to a workspace buffer W that is zero between calls.
-// Each workgroup makes its scatter and its partial of f visible device-wide
-// and takes a ticket; the last workgroup to take one writes grad from W (or
-// adds W into it), clears W for the next call, sums the partials in their
-// fixed order into f and re-arms the ticket.  The grid is at most
-// kSmallMaxBlocks workgroups, so the one device-scope fence per thread is
-// cheap.  No workgroup waits for another.
+// Once a workgroup's scatter is visible device-wide it counts itself done on
+// each node range it touched (the plan lists them); the last workgroup done
+// on a range writes grad there from W (or adds W into it) and clears W there
+// for the next call, so that work is spread over the grid instead of left to
+// one workgroup.  Each workgroup's partial of f goes the same way through a
+// single ticket: the last workgroup sums the partials in their fixed order.
+// The grid is at most kSmallMaxBlocks workgroups, so the device-scope fences
+// are cheap.  No workgroup waits for another.
 #include "device_common.hpp"
 #include "elem_tile.hpp"
 #include "launch.hpp"
@@ -18,8 +20,6 @@
 namespace pg {
 
 namespace {
-
-constexpr int kSmallU = 8;  // W entries a thread has in flight in the last workgroup
 
 template <typename T, int K, int MODE, int AGG>
 __global__ void __launch_bounds__(1024)
@@ -36,42 +36,75 @@ k_mesh_small(MeshView m, MeshPass p, SmallPass sp) {
     AggOf<AGG>* tab = nullptr;
     if constexpr (AGG > 0) tab = &agg;
     const double tsum = elem_tile<T, K, MODE, 1, AGG>(a, (int64_t)lb * bs, m.n_elems, 0, fb, tab);
-    if constexpr (has_rev(MODE)) __threadfence();  // this thread's atomics are visible
+    // Publication costs one device-scope fence per workgroup, not one per
+    // wave: every wave first waits until its own atomics are performed, then
+    // wave 0 (after the barrier) writes the partial, releases at device scope
+    // and takes the counts.  The L2 write-back of its release covers the
+    // whole workgroup's completed atomics.
+    if constexpr (has_rev(MODE)) __builtin_amdgcn_s_waitcnt(0);
     double s = 0.0;
     if constexpr (has_sum(MODE)) s = block_sum_dyn(tsum, lds);
-    if (threadIdx.x == 0) {
-        if constexpr (has_sum(MODE)) p.partials[lb] = s;
-        __threadfence();  // the workgroup's partial and scatter before its ticket
-        last = atomicAdd(sp.ticket, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    __shared__ int fin[kSmallMaxRanges];
+    __shared__ int any_fin;
+    int r0 = 0, nr = 0;
+    if constexpr (has_rev(MODE)) {
+        r0 = sp.wg_off[lb];
+        nr = sp.wg_off[lb + 1] - r0;
+    }
+    if (threadIdx.x < kWave) {
+        if constexpr (has_sum(MODE))
+            if (threadIdx.x == 0) p.partials[lb] = s;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if constexpr (has_rev(MODE)) {
+            bool mine = false;
+            if ((int)threadIdx.x < nr) {
+                const int r = sp.wg_list[r0 + threadIdx.x];
+                mine = atomicAdd(sp.range_done + r, 1) == sp.range_need[r] - 1;
+                fin[threadIdx.x] = mine;
+            }
+            const bool any = __any(mine);
+            if (threadIdx.x == 0) any_fin = any;
+        }
+        if constexpr (has_sum(MODE))
+            if (threadIdx.x == 0) last = atomicAdd(sp.ticket, 1) == (int)gridDim.x - 1;
     }
     __syncthreads();
-    if (!last) return;
-    __threadfence();  // every workgroup's scatter and partial are visible
     if constexpr (has_rev(MODE)) {
-        T* __restrict__ g = static_cast<T*>(sp.grad);
-        double* __restrict__ W = p.gacc;
-        const int64_t n = m.n_nodes;
-        for (int64_t q = threadIdx.x; q < n; q += kSmallU * bs) {
-            double v[kSmallU];
-#pragma unroll
-            for (int u = 0; u < kSmallU; ++u) v[u] = q + u * bs < n ? W[q + u * bs] : 0.0;
-#pragma unroll
-            for (int u = 0; u < kSmallU; ++u) {
-                const int64_t i = q + u * bs;
-                if (i < n) {
-                    W[i] = 0.0;
-                    g[i] = sp.accumulate ? static_cast<T>(to_f64(g[i]) + v[u]) : static_cast<T>(v[u]);
+        if (any_fin) {
+            // Last on some ranges: every scatter into them is visible after
+            // wave 0's acquire (the caches it invalidates serve all waves).
+            if (threadIdx.x < kWave) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __syncthreads();
+            T* __restrict__ g = static_cast<T*>(sp.grad);
+            double* __restrict__ W = p.gacc;
+            for (int i = 0; i < nr; ++i) {
+                if (!fin[i]) continue;
+                const int r = sp.wg_list[r0 + i];
+                const int64_t n0 = (int64_t)r * kSmallRange;
+                const int64_t n1 = n0 + kSmallRange < m.n_nodes ? n0 + kSmallRange : m.n_nodes;
+                for (int64_t q = n0 + threadIdx.x; q < n1; q += bs) {
+                    const double v = W[q];
+                    W[q] = 0.0;
+                    g[q] = sp.accumulate ? static_cast<T>(to_f64(g[q]) + v) : static_cast<T>(v);
                 }
+                if (threadIdx.x == 0) sp.range_done[r] = 0;
             }
         }
     }
     if constexpr (has_sum(MODE)) {
-        double v = 0.0;
-        for (int q = threadIdx.x; q < (int)gridDim.x; q += (int)bs) v += p.partials[q];
-        v = block_sum_dyn(v, lds);
-        if (threadIdx.x == 0 && sp.f_out) sp.f_out[0] = v;
+        if (last) {
+            if (threadIdx.x < kWave) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __syncthreads();
+            double v = 0.0;
+            for (int q = threadIdx.x; q < (int)gridDim.x; q += (int)bs) v += p.partials[q];
+            v = block_sum_dyn(v, lds);
+            if (threadIdx.x == 0) {
+                if (sp.f_out) sp.f_out[0] = v;
+                *sp.ticket = 0;
+            }
+        }
     }
-    if (threadIdx.x == 0) *sp.ticket = 0;
 }
 
 template <typename T, int K, int MODE>
@@ -123,7 +156,9 @@ bool mesh_small_eligible(const MeshView& m, int block) {
 hipError_t launch_mesh_small(const MeshView& m, MeshMode mode, const MeshPass& p,
                              const SmallPass& sp, hipStream_t s) {
     if (!mesh_small_eligible(m, p.block) || !sp.ticket) return hipErrorInvalidValue;
-    if (mode != M_PRIMAL && (!p.gacc || !sp.grad)) return hipErrorInvalidValue;
+    if (mode != M_PRIMAL && (!p.gacc || !sp.grad || !sp.range_done || !sp.range_need ||
+                             !sp.wg_off || !sp.wg_list))
+        return hipErrorInvalidValue;
     return m.dtype == F64 ? launch_small_k<double>(m, mode, p, sp, s)
                           : launch_small_k<float>(m, mode, p, sp, s);
 }
