@@ -51,7 +51,7 @@ def plan_mesh(n_nodes=10, n_elems=4, k=8, conn=FAKE, B=FAKE, w=FAKE, dtype=P.F64
 
 
 def test_mesh_plan_is_host_only_and_sizes_workspace():
-    st, plan, ws = plan_mesh(n_nodes=1000, n_elems=900, k=8)
+    st, plan, ws = plan_mesh(n_nodes=1000, n_elems=900, k=8, opts=P.make_options(onepass=False))
     assert st == P.OK and ws > 0 and ws % P.WORKSPACE_ALIGN == 0
     st2, plan2, ws2 = plan_mesh(n_nodes=1000, n_elems=900, k=8,
                                 opts=P.make_options("gather", "store"))
