@@ -321,12 +321,16 @@ typedef struct {
     int32_t groups;           /* fused groups of pointwise constructs (the sum's included) */
     int32_t fused_gathers;    /* gathers evaluated inside their consuming group */
     int32_t dead_ops;         /* constructs that do not feed the sum (never run) */
+    int32_t folded_ops;       /* scales folded into the coefficients of the one
+                                 stencil that reads them (fusion 1) */
     int64_t tape_bytes;       /* forward values recorded between kernels */
     int64_t workspace_bytes;
 } pg_prog_stats;
 
-/* Fusion level, before pg_prog_plan.  1 (default): chains of pointwise
- * constructs (scale, add, mul, map) run as one kernel per group, keep their
+/* Fusion level, before pg_prog_plan.  1 (default): a scale read only by a
+ * stencil is folded into the stencil's coefficients (the two are linear);
+ * chains of pointwise constructs (scale, add, mul, map) run as one kernel
+ * per group, keep their
  * intermediates in registers and recompute them in the reverse pass (no
  * tape); a gather read only by one group runs inside it, its reverse being
  * an LDS-combined atomic scatter; the group holding the sum runs its

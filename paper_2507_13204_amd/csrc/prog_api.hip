@@ -46,6 +46,8 @@ struct Op {
     double alpha = 1.0, beta = 1.0;
     int fn = 0;
     ProgTaps taps;
+    int32_t a0 = -1;        // operand and taps as built (the plan may fold a scale into a stencil)
+    ProgTaps taps0;
     int32_t k = 0;
     const int32_t* conn = nullptr;
     const double* B = nullptr;
@@ -60,6 +62,7 @@ struct Op {
     bool fused = false;      // a gather evaluated inside its consuming group
     bool stored = false;     // forward value materialised
     bool exported = false;   // group member read from outside its group
+    bool folded = false;     // a scale folded into the stencil reading it
     size_t val_off = NONE;   // forward value in the workspace (intermediates)
     size_t shd_off = NONE;   // shadow in the workspace (active intermediates)
 };
@@ -114,6 +117,8 @@ pg_status add_view(pg_prog p, const Op& op, int32_t* view) {
     if (p->sum_view >= 0) return perr(PG_ESTATE, "the program already ended with pg_prog_sum");
     if (!view) return perr(PG_EINVAL, "view is NULL");
     p->ops.push_back(op);
+    p->ops.back().a0 = op.a;
+    p->ops.back().taps0 = op.taps;
     p->planned = false;
     *view = (int32_t)p->ops.size() - 1;
     return PG_OK;
@@ -330,6 +335,31 @@ pg_status pg_prog_plan(pg_prog p, size_t* workspace_bytes) {
     if (p->sum_view < 0) return perr(PG_ESTATE, "the program has no pg_prog_sum");
     std::vector<Op>& ops = p->ops;
     const int32_t nv = (int32_t)ops.size(), S = p->sum_view;
+    for (Op& op : ops) {
+        op.a = op.a0;
+        op.taps = op.taps0;
+        op.folded = false;
+    }
+    // A scale whose only reader is a stencil folds into the stencil's
+    // coefficients: c (alpha a) = (c alpha) a, forward and reverse alike.
+    if (p->fusion) {
+        std::vector<int32_t> readers((size_t)nv, 0);
+        for (const Op& op : ops) {
+            if (op.a >= 0) readers[(size_t)op.a]++;
+            if (op.b >= 0) readers[(size_t)op.b]++;
+        }
+        readers[(size_t)S]++;
+        for (int32_t v = 0; v < nv; ++v) {
+            Op& st = ops[(size_t)v];
+            if (st.kind != P_STENCIL) continue;
+            while (ops[(size_t)st.a].kind == P_SCALE && readers[(size_t)st.a] == 1) {
+                Op& sc = ops[(size_t)st.a];
+                for (int t = 0; t < st.taps.n; ++t) st.taps.coef[t] *= sc.alpha;
+                sc.folded = true;
+                st.a = sc.a;  // the scale's own read of its operand moves to the stencil
+            }
+        }
+    }
     // Liveness: only what feeds the summed view runs.
     for (Op& op : ops) {
         op.live = false;
@@ -598,8 +628,10 @@ pg_status pg_prog_plan(pg_prog p, size_t* workspace_bytes) {
         }
     }
     st.fwd_kernels += 1;  // the fixed-order reduction of the sum's partials
-    for (const Op& op : ops)
-        if (!op.live && op.kind != P_INPUT && op.kind != P_CONST) ++st.dead_ops;
+    for (const Op& op : ops) {
+        if (op.folded) ++st.folded_ops;
+        else if (!op.live && op.kind != P_INPUT && op.kind != P_CONST) ++st.dead_ops;
+    }
     st.tape_bytes = p->tape_bytes;
     st.workspace_bytes = (int64_t)p->ws_bytes;
     p->planned = true;

@@ -55,8 +55,8 @@ class ProgStats(ctypes.Structure):
     _fields_ = [("fwd_kernels", ctypes.c_int32), ("rev_kernels", ctypes.c_int32),
                 ("atomic_ops", ctypes.c_int32), ("rescheduled_ops", ctypes.c_int32),
                 ("groups", ctypes.c_int32), ("fused_gathers", ctypes.c_int32),
-                ("dead_ops", ctypes.c_int32), ("tape_bytes", ctypes.c_int64),
-                ("workspace_bytes", ctypes.c_int64)]
+                ("dead_ops", ctypes.c_int32), ("folded_ops", ctypes.c_int32),
+                ("tape_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
 
 
 class Options(ctypes.Structure):

@@ -304,6 +304,47 @@ def test_mesh_program_plan(fusion):
     L.pg_prog_destroy(p)
 
 
+@pytest.mark.parametrize("fusion", [0, 1])
+def test_scale_folds_into_the_stencil_that_reads_it(fusion):
+    """The section 4 example as constructs: with fusion the scale by 3 folds
+    into the stencil's coefficients, so the forward pass is the stencil, the
+    group (subtract b, square, sum) and the final reduction, and the reverse
+    the rescheduled stencil; a scale with a second reader does not fold."""
+    L, p = _prog()
+    assert L.pg_prog_fusion(p, fusion) == P.OK
+    n = 1000
+    _, x = _v(L.pg_prog_input, p, n)
+    _, b = _v(L.pg_prog_input, p, n)
+    _, sx = _v(L.pg_prog_scale, p, x, 3.0)
+    off = (ctypes.c_int32 * 3)(-1, 0, 1)
+    cf = (ctypes.c_double * 3)(-1.0, 2.0, -1.0)
+    _, y = _v(L.pg_prog_stencil, p, sx, 3, off, cf)
+    _, r = _v(L.pg_prog_add, p, y, 1.0, b, -1.0)
+    _, q = _v(L.pg_prog_map, p, r, 0)
+    assert L.pg_prog_sum(p, q) == P.OK
+    sz = ctypes.c_size_t()
+    assert L.pg_prog_plan(p, ctypes.byref(sz)) == P.OK
+    st = P.ProgStats()
+    assert L.pg_prog_info(p, ctypes.byref(st)) == P.OK
+    assert st.dead_ops == 0 and st.rescheduled_ops == 1
+    if fusion:
+        assert (st.folded_ops, st.groups, st.fwd_kernels, st.rev_kernels) == (1, 1, 3, 1)
+    else:
+        assert (st.folded_ops, st.groups, st.fwd_kernels, st.rev_kernels) == (0, 3, 5, 4)
+    L.pg_prog_destroy(p)
+    # a second reader of the scale keeps it
+    L, p = _prog()
+    _, x = _v(L.pg_prog_input, p, n)
+    _, sx = _v(L.pg_prog_scale, p, x, 3.0)
+    _, y = _v(L.pg_prog_stencil, p, sx, 3, off, cf)
+    _, m = _v(L.pg_prog_mul, p, y, sx)
+    assert L.pg_prog_sum(p, m) == P.OK
+    assert L.pg_prog_plan(p, ctypes.byref(sz)) == P.OK
+    assert L.pg_prog_info(p, ctypes.byref(st)) == P.OK
+    assert st.folded_ops == 0
+    L.pg_prog_destroy(p)
+
+
 def test_program_fusion_level_is_checked():
     L, p = _prog()
     assert L.pg_prog_fusion(p, 2) == P.EINVAL
