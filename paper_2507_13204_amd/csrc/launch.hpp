@@ -365,6 +365,10 @@ struct GroupDev {
     double* export_val[kGExports] = {};
     const double* export_shadow[kGExports] = {};
     double* partials = nullptr;
+    // Sum group of a small grid: the last workgroup to take the ticket (zero
+    // between launches; re-armed by that workgroup) sums the partials into f.
+    int32_t* ticket = nullptr;
+    double* f_out = nullptr;
 };
 
 enum GroupMode { G_FWD = 0, G_REV = 1, G_FWDREV = 2 };

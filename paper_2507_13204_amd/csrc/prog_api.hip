@@ -100,6 +100,7 @@ struct pg_prog_s {
     std::vector<Group> groups;
     std::vector<Item> sched;                       // forward order
     int32_t sum_group = -1;
+    bool sum_ticket = false;  // the sum group's last workgroup writes f (no reduction launch)
     std::vector<int32_t> zero_views;               // shadows cleared before the reverse pass
     std::vector<int32_t> op_acc;                   // per view: delivery of a construct's reverse
     std::vector<std::vector<int32_t>> leaf_acc;    // per group, per leaf
@@ -627,7 +628,10 @@ pg_status pg_prog_plan(pg_prog p, size_t* workspace_bytes) {
             if (op.kind == P_STENCIL && op.taps.n > 1) ++st.rescheduled_ops;
         }
     }
-    st.fwd_kernels += 1;  // the fixed-order reduction of the sum's partials
+    // The fixed-order reduction of the sum's partials: a launch of its own,
+    // or (fused, at most 64 workgroups) the sum group's last workgroup.
+    p->sum_ticket = p->fusion && ops[(size_t)S].n > 0 && ops[(size_t)S].n <= 64 * (int64_t)kGroupBlock;
+    if (!p->sum_ticket) st.fwd_kernels += 1;
     for (const Op& op : ops) {
         if (op.folded) ++st.folded_ops;
         else if (!op.live && op.kind != P_INPUT && op.kind != P_CONST) ++st.dead_ops;
@@ -764,6 +768,10 @@ pg_status pg_prog_run(pg_prog p, const double* const* inputs, double* f_out, dou
             d.sum_slot = slot(p->sum_view);
             d.partials = partials;
             d.seed = fbar;
+            if (p->sum_ticket) {
+                d.ticket = reinterpret_cast<int32_t*>(p->ws + p->flag_off) + 1;  // zeroed at bind
+                d.f_out = f_out ? f_out : at(p, p->fscratch_off);
+            }
         }
         if (g.gather >= 0) {
             const Op& go = ops[(size_t)g.gather];
@@ -818,7 +826,8 @@ pg_status pg_prog_run(pg_prog p, const double* const* inputs, double* f_out, dou
             PG_HIP(launch_prog_fwd(op_dev(it.id), s));
         }
     }
-    PG_HIP(launch_final_sum(partials, n_partials, f_out ? f_out : at(p, p->fscratch_off), s));
+    if (!p->sum_ticket)
+        PG_HIP(launch_final_sum(partials, n_partials, f_out ? f_out : at(p, p->fscratch_off), s));
     if (!rev) return PG_OK;
     // Reverse pass: the schedule backwards, reads turned into deliveries.
     for (size_t r = p->sched.size(); r-- > 0;) {

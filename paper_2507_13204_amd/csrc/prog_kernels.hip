@@ -285,6 +285,7 @@ __global__ void __launch_bounds__(BS) k_group(GroupDev g) {
     static_assert(AGG == (S > 0), "a table exactly when the reverse scatters a fused gather");
     constexpr int NL = NS < kGLeaves ? NS : kGLeaves;
     __shared__ double lds[BS / kWave];
+    __shared__ int last_wg;
     __shared__ typename std::conditional<AGG, AggTableT<S>, int>::type tab;
     const bool scatter = AGG && g.gsrc_shadow != nullptr;
     const int64_t i = xcd_remap(blockIdx.x, gridDim.x) * BS + threadIdx.x;
@@ -395,6 +396,25 @@ __global__ void __launch_bounds__(BS) k_group(GroupDev g) {
                 }
                 __syncthreads();
                 agg_flush(tab, g.gsrc_shadow);
+            }
+        }
+    }
+    if constexpr (FWD) {
+        if (g.sum_slot >= 0 && g.ticket) {
+            if (threadIdx.x == 0) {
+                __threadfence();  // this workgroup's partial before its ticket
+                last_wg = atomicAdd(g.ticket, 1) == (int)gridDim.x - 1;
+            }
+            __syncthreads();
+            if (last_wg) {
+                __threadfence();  // every partial is visible
+                double v = 0.0;
+                for (int q = threadIdx.x; q < (int)gridDim.x; q += BS) v += g.partials[q];
+                v = block_sum<BS>(v, lds);
+                if (threadIdx.x == 0) {
+                    *g.f_out = v;
+                    *g.ticket = 0;
+                }
             }
         }
     }

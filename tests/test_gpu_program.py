@@ -299,3 +299,28 @@ def test_program_run_replays_from_a_graph():
         assert srel(f.item(), f_e.item()) < 1e-14
         for a, b in zip(gs, g_e):
             assert rel(a.cpu().numpy(), b.cpu().numpy()) < 1e-13
+
+
+@pytest.mark.parametrize("n", [300, 16_384, 16_385])
+def test_small_sum_reduced_by_its_last_workgroup(n):
+    """Up to 64 summing workgroups (16,384 summed entries) the sum group's last
+    workgroup reduces f through a ticket it re-arms; objective-only and
+    gradient runs alternate on one plan and every f is the same, bitwise, and
+    the oracle's; one more entry takes the separate reduction launch."""
+    case = inputs.program_paper(n, seed=21)
+    prog = P.Program.from_spec(case.spec).plan()
+    xs = [to_dev(x) for x in case.inputs]
+    f_ref, g_ref = OP.gradient(case.spec, case.inputs)
+    fs = []
+    for i in range(4):
+        if i % 2 == 0:
+            f, gs = prog.run(xs, grads=True)
+            for g, gr in zip(gs, g_ref):
+                assert rel(g.cpu().numpy(), gr) < TOL_F64_G
+        else:
+            f = prog.run(xs, grads=False)
+        fs.append(f.item())
+    assert srel(fs[0], f_ref) < TOL_F64_F
+    assert all(v == fs[0] for v in fs)
+    # the fused reduction saves the launch (forward: the stencil and the group)
+    assert prog.info()["fwd_kernels"] == (2 if n <= 16_384 else 3)
