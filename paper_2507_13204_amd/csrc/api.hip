@@ -465,6 +465,7 @@ pg_status check_out_alias(pg_plan p, const void* out, size_t out_bytes, const vo
                 overlap(out, out_bytes, p->bd.W, es * (size_t)(p->bd.m * p->bd.n)))
                 return fail(PG_EALIAS, "%s overlaps A or W", what);
             break;
+        case K_LAPLACE: break;  // its entry points check their own operands
     }
     return PG_OK;
 }
@@ -561,8 +562,9 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
     if (p->opt.adjoint == PG_ADJ_COLOUR) {
         // Elements of one colour share no node: plain read-add-write, one
         // pass per colour in a fixed order (deterministic).
+        // FP32: the FP64 buffer is zero between calls (cleared by the conversion)
         q.gacc = f32 ? p->at<double>(p->o_gacc) : static_cast<double*>(grad);
-        if (f32 || !acc) PG_HIP(launch_zero(q.gacc, sizeof(double) * (size_t)m.n_nodes, s));
+        if (!f32 && !acc) PG_HIP(launch_zero(q.gacc, sizeof(double) * (size_t)m.n_nodes, s));
         const int32_t* elist = p->at<int32_t>(p->o_elist);
         int64_t slot = 0;
         PG_HIP(tmark(p, 1, true, s));
@@ -576,7 +578,7 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
         }
         PG_HIP(tmark(p, 1, false, s));
         if (f32)
-            PG_HIP(launch_f64_to_f32(q.gacc, static_cast<float*>(grad), m.n_nodes, acc, s));
+            PG_HIP(launch_f64_to_f32(q.gacc, static_cast<float*>(grad), m.n_nodes, acc, 1, s));
         if (obj && f_out) PG_HIP(launch_final_sum(q.partials, slot, f_out, s));
         return PG_OK;
     }
@@ -600,8 +602,7 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
         PG_HIP(tmark(p, 1, false, s));
     } else {  // atomic
         if (f32) {
-            q.gacc = p->at<double>(p->o_gacc);
-            PG_HIP(launch_zero(q.gacc, sizeof(double) * (size_t)m.n_nodes, s));
+            q.gacc = p->at<double>(p->o_gacc);  // zero between calls (cleared by the conversion)
         } else {
             q.gacc = static_cast<double*>(grad);
             if (!acc) PG_HIP(launch_zero(grad, sizeof(double) * (size_t)m.n_nodes, s));
@@ -610,7 +611,7 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
         PG_HIP(launch_mesh_elem(m, obj ? M_GRAD_ATOMIC : M_ADJ_ATOMIC, q, s));
         PG_HIP(tkern(p, false));
         if (f32)
-            PG_HIP(launch_f64_to_f32(q.gacc, static_cast<float*>(grad), m.n_nodes, acc, s));
+            PG_HIP(launch_f64_to_f32(q.gacc, static_cast<float*>(grad), m.n_nodes, acc, 1, s));
         if (obj && f_out) PG_HIP(launch_final_sum(q.partials, p->mesh_blocks_n, f_out, s));
         return PG_OK;
     }
@@ -823,6 +824,8 @@ pg_status mesh_bind(pg_plan p, hipStream_t s) {
     const MeshView& m = p->mesh;
     int32_t* flag = p->at<int32_t>(p->o_flag);
     PG_HIP(launch_zero(flag, sizeof(int32_t) * 4, s));
+    // FP32 plans: the FP64 accumulation buffer is zero between calls.
+    if (p->o_gacc != NONE) PG_HIP(launch_zero(p->at<double>(p->o_gacc), sizeof(double) * (size_t)m.n_nodes, s));
     const int64_t items = m.n_elems * m.k;
     if (p->opt.adjoint == PG_ADJ_GATHER) {
         int32_t* cnt = p->at<int32_t>(p->o_cursor);
@@ -881,6 +884,9 @@ pg_status mesh_bind(pg_plan p, hipStream_t s) {
 pg_status batch_bind(pg_plan p, hipStream_t s) {
     int32_t* flag = p->at<int32_t>(p->o_flag);
     PG_HIP(launch_zero(flag, sizeof(int32_t) * 4, s));
+    // FP32 plans: the FP64 accumulation buffer is zero between calls.
+    if (p->o_gacc != NONE)
+        PG_HIP(launch_zero(p->at<double>(p->o_gacc), sizeof(double) * (size_t)p->n_nodes_total, s));
     // Validate each instance's connectivity against its own node count.
     for (const pg_instance& in : p->inst) {
         if (in.n_elems == 0) continue;
@@ -956,8 +962,7 @@ pg_status batch_run(pg_plan p, const void* x, const double* fbar, void* grad, do
         q.u_in = p->at<double>(p->o_u);
     }
     if (f32) {
-        q.grad = p->at<double>(p->o_gacc);
-        PG_HIP(launch_zero(q.grad, sizeof(double) * (size_t)p->n_nodes_total, s));
+        q.grad = p->at<double>(p->o_gacc);  // zero between calls (cleared by the conversion)
     } else {
         q.grad = grad;
         if (!acc) PG_HIP(launch_zero(grad, sizeof(double) * (size_t)p->n_nodes_total, s));
@@ -966,8 +971,8 @@ pg_status batch_run(pg_plan p, const void* x, const double* fbar, void* grad, do
     PG_HIP(launch_batch(p->batch, obj ? B_GRAD_ATOMIC : B_ADJ_ATOMIC, q, s));
     PG_HIP(tkern(p, false));
     if (f32)
-        PG_HIP(launch_f64_to_f32((const double*)q.grad, static_cast<float*>(grad),
-                                 p->n_nodes_total, acc, s));
+        PG_HIP(launch_f64_to_f32(static_cast<double*>(q.grad), static_cast<float*>(grad), p->n_nodes_total,
+                                 acc, 1, s));
     if (obj && f_out) PG_HIP(launch_segmented_sum(q.partials, seg, ni, f_out, s));
     return PG_OK;
 }
@@ -1295,10 +1300,11 @@ pg_status pg_hvp(pg_plan p, const void* x, const void* v, void* hv, pg_stream st
     MeshPass q = base_pass(p, x);
     q.xd = v;
     const bool f32 = p->dtype == PG_F32;
-    q.gacc = f32 ? p->at<double>(p->o_gacc) : static_cast<double*>(hv);
-    if (f32 || !p->opt.accumulate) PG_HIP(launch_zero(q.gacc, sizeof(double) * (size_t)m.n_nodes, s));
+    q.gacc = f32 ? p->at<double>(p->o_gacc) : static_cast<double*>(hv);  // FP32: zero between calls
+    if (!f32 && !p->opt.accumulate) PG_HIP(launch_zero(q.gacc, sizeof(double) * (size_t)m.n_nodes, s));
     PG_HIP(launch_mesh_elem(m, M_HVP, q, s));
-    if (f32) PG_HIP(launch_f64_to_f32(q.gacc, static_cast<float*>(hv), m.n_nodes, p->opt.accumulate, s));
+    if (f32)
+        PG_HIP(launch_f64_to_f32(q.gacc, static_cast<float*>(hv), m.n_nodes, p->opt.accumulate, 1, s));
     return PG_OK;
 }
 
@@ -1427,7 +1433,7 @@ pg_status pg_laplace1d_gradient(pg_plan p, const void* x, const void* b, void* g
         PG_HIP(launch_laplace1d(p->lap_n, dt, 2, x, b, g64, nullptr, gb, nullptr, partials, acc,
                                 ticket, f_out, s));
         PG_HIP(tkern(p, false));
-        if (gx && dt == F32) PG_HIP(launch_f64_to_f32(g64, static_cast<float*>(gx), p->lap_n, acc, s));
+        if (gx && dt == F32) PG_HIP(launch_f64_to_f32(g64, static_cast<float*>(gx), p->lap_n, acc, 0, s));
     } else {
         PG_HIP(tkern(p, true));
         PG_HIP(launch_laplace1d(p->lap_n, dt, 1, x, b, nullptr, gx, gb, nullptr, partials, acc,

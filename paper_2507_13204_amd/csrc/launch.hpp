@@ -152,8 +152,8 @@ hipError_t launch_segmented_sum(const double* partials, const int64_t* seg, int6
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 
-// dst (FP32) (=|+=) src (FP64).
-hipError_t launch_f64_to_f32(const double* src, float* dst, int64_t n, int accumulate,
+// dst (FP32) (=|+=) src (FP64); clear: src is zeroed as it is read.
+hipError_t launch_f64_to_f32(double* src, float* dst, int64_t n, int accumulate, int clear,
                              hipStream_t s);
 // dst (FP64) += src (FP64).
 hipError_t launch_add_f64(const double* src, double* dst, int64_t n, hipStream_t s);

@@ -67,11 +67,15 @@ __global__ void __launch_bounds__(256) k_zero1(uint8_t* __restrict__ p, int64_t 
     if (i < n) p[i] = 0;
 }
 
+// dst (FP32) (=|+=) src (FP64); with clear, src is left zero for the next call.
 __global__ void __launch_bounds__(256)
-k_f64_to_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t n, int accumulate) {
+k_f64_to_f32(double* __restrict__ src, float* __restrict__ dst, int64_t n, int accumulate, int clear) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        dst[i] = accumulate ? static_cast<float>((double)dst[i] + src[i]) : static_cast<float>(src[i]);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double v = src[i];
+        if (clear) src[i] = 0.0;
+        dst[i] = accumulate ? static_cast<float>((double)dst[i] + v) : static_cast<float>(v);
+    }
 }
 
 __global__ void __launch_bounds__(256)
@@ -243,11 +247,11 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_f64_to_f32(const double* src, float* dst, int64_t n, int accumulate,
+hipError_t launch_f64_to_f32(double* src, float* dst, int64_t n, int accumulate, int clear,
                              hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_f64_to_f32, dim3(stream_grid(n, 256 * 4, 8192)), dim3(256), 0, s, src,
-                       dst, n, accumulate);
+                       dst, n, accumulate, clear);
     return hipGetLastError();
 }
 

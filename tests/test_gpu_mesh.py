@@ -360,3 +360,30 @@ def test_one_launch_small_meshes(name, dtype):
     acc.gradient(x, out=base)
     acc.gradient(x, out=base)
     assert rel(base.cpu().numpy().astype(np.float64), 3.0 * g.cpu().numpy().astype(np.float64)) <= tol_g
+
+
+@pytest.mark.parametrize("adj", ["atomic", "colour"])
+def test_f32_accumulation_buffer_is_clear_between_calls(adj):
+    """FP32 plans accumulate in an FP64 buffer that the conversion to FP32
+    leaves zero for the next call (no fill launch): gradient, seeded adjoint,
+    HVP and accumulating calls interleaved on one plan all match the oracle."""
+    m = MESHES["hex23"]().astype(np.float32)
+    mm = inputs.Mesh(m.n_nodes, m.n_elems, m.k, m.conn, m.B, m.w, m.x, m.name)
+    obj, x = _obj(mm, "f32", adjoint=adj, onepass=False)
+    d = inputs.fd_directions((m.n_nodes,), 1, seed=17)[0].astype(np.float32)
+    dd = to_dev(d)
+    _, g_ref = _oracle_grad(mm, "f32")
+    h_ref = oracle.mesh_hvp(m.n_nodes, m.conn, m.B.astype(np.float64), m.w.astype(np.float64),
+                            m.x.astype(np.float64), d.astype(np.float64))
+    fbar = torch.tensor([2.0], dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        f, g = obj.gradient(x)
+        assert rel(g.cpu().numpy().astype(np.float64), g_ref) <= TOL_F32
+        assert rel(obj.adjoint(x, fbar).cpu().numpy().astype(np.float64), 2.0 * g_ref) <= TOL_F32
+        if adj == "atomic":
+            assert rel(obj.hvp(x, dd).cpu().numpy().astype(np.float64), h_ref) <= TOL_F32
+    acc, _ = _obj(mm, "f32", adjoint=adj, accumulate=True, onepass=False)
+    base = torch.zeros_like(x)
+    for _ in range(3):
+        acc.gradient(x, out=base)
+    assert rel(base.cpu().numpy().astype(np.float64), 3.0 * g_ref) <= TOL_F32
