@@ -190,7 +190,11 @@ pg_status pg_workspace_size(pg_plan plan, size_t* workspace_bytes);
  * aligned to PG_WORKSPACE_ALIGN, to the plan; validate the connectivity
  * (PG_ERANGE if an entry is outside [0, n_nodes)) and build the plan's
  * device structures (transposed connectivity, colour classes, work lists).
- * Enqueued on stream and WAITS for it.  Rebinding is allowed. */
+ * Enqueued on stream and WAITS for it.  Rebinding is allowed.  Some parts of
+ * the workspace are set to zero here and every call leaves them zero again
+ * (the FP64 accumulation buffer of FP32 plans, the buffers and counters of
+ * one-launch calls): the caller must not write to a bound workspace, and
+ * after a call that failed with PG_EHIP the plan should be bound again. */
 pg_status pg_bind_workspace(pg_plan plan, void* workspace, size_t bytes, pg_stream stream);
 
 /* ------------------------------------------------------------- evaluation */
