@@ -113,8 +113,8 @@ typedef struct {
                            (2 and 3: single meshes; batches treat them as 0) */
     int32_t onepass;    /* single meshes, atomic adjoint, k = 2, 4 or 8: 0 =
                            default (a mesh of at most 64 workgroups and 16,384
-                           nodes runs each objective, gradient or adjoint call
-                           as one launch: the contributions gather in a
+                           nodes runs each objective, gradient, adjoint, HVP
+                           or JVP call as one launch: the contributions gather in a
                            workspace buffer and the last workgroup to finish
                            writes grad from it, clears it and sums f), 1 = the
                            multi-launch path at every size */

@@ -500,6 +500,18 @@ TiledView tiled_view(pg_plan p) {
     return v;
 }
 
+// The one-launch path's counters and tables in the workspace.
+SmallPass small_pass(pg_plan p) {
+    SmallPass sp;
+    int32_t* meta = p->at<int32_t>(p->o_small_meta);
+    sp.ticket = p->at<int32_t>(p->o_ticket);
+    sp.range_done = meta;
+    sp.range_need = meta + kSmallMaxRanges;
+    sp.wg_off = meta + 2 * kSmallMaxRanges;
+    sp.wg_list = sp.wg_off + (kSmallMaxBlocks + 1);
+    return sp;
+}
+
 pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, double* f_out,
                    int want, hipStream_t s) {
     const MeshView& m = p->mesh;
@@ -511,13 +523,7 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
     if (p->small) {
         // One launch: the element work, the scatter into the zeroed buffer,
         // and (last workgroup) grad from the buffer, the buffer cleared, f.
-        SmallPass sp;
-        int32_t* meta = p->at<int32_t>(p->o_small_meta);
-        sp.ticket = p->at<int32_t>(p->o_ticket);
-        sp.range_done = meta;
-        sp.range_need = meta + kSmallMaxRanges;
-        sp.wg_off = meta + 2 * kSmallMaxRanges;
-        sp.wg_list = sp.wg_off + (kSmallMaxBlocks + 1);
+        SmallPass sp = small_pass(p);
         sp.accumulate = acc;
         sp.f_out = obj ? f_out : nullptr;
         MeshMode mode = M_PRIMAL;
@@ -1299,6 +1305,14 @@ pg_status pg_hvp(pg_plan p, const void* x, const void* v, void* hv, pg_stream st
     const MeshView& m = p->mesh;
     MeshPass q = base_pass(p, x);
     q.xd = v;
+    if (p->small) {  // one launch: the scatter into the zeroed buffer, hv written range by range
+        SmallPass sp = small_pass(p);
+        sp.grad = hv;
+        sp.accumulate = p->opt.accumulate;
+        q.gacc = p->at<double>(p->o_small);
+        PG_HIP(launch_mesh_small(m, M_HVP, q, sp, s));
+        return PG_OK;
+    }
     const bool f32 = p->dtype == PG_F32;
     q.gacc = f32 ? p->at<double>(p->o_gacc) : static_cast<double*>(hv);  // FP32: zero between calls
     if (!f32 && !p->opt.accumulate) PG_HIP(launch_zero(q.gacc, sizeof(double) * (size_t)m.n_nodes, s));
@@ -1457,6 +1471,12 @@ pg_status pg_jvp(pg_plan p, const void* x, const void* d, double* jvp_out, pg_st
     hipStream_t s = static_cast<hipStream_t>(stream);
     MeshPass q = base_pass(p, x);
     q.xd = d;
+    if (p->small) {  // one launch: the last workgroup sums the partials
+        SmallPass sp = small_pass(p);
+        sp.f_out = jvp_out;
+        PG_HIP(launch_mesh_small(p->mesh, M_JVP, q, sp, s));
+        return PG_OK;
+    }
     PG_HIP(launch_mesh_elem(p->mesh, M_JVP, q, s));
     PG_HIP(launch_final_sum(q.partials, p->mesh_blocks_n, jvp_out, s));
     return PG_OK;

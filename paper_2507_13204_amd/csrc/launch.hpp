@@ -104,7 +104,8 @@ constexpr int64_t kSmallMaxNodes = 16384;
 constexpr int kSmallRange = 512;
 constexpr int kSmallMaxRanges = (int)(kSmallMaxNodes / kSmallRange);
 bool mesh_small_eligible(const MeshView& m, int block);
-// mode: M_PRIMAL, M_GRAD_ATOMIC or M_ADJ_ATOMIC.
+// mode: M_PRIMAL, M_GRAD_ATOMIC, M_ADJ_ATOMIC, M_HVP (scatters like the
+// gradient) or M_JVP (sums like the objective).
 hipError_t launch_mesh_small(const MeshView& m, MeshMode mode, const MeshPass& p,
                              const SmallPass& sp, hipStream_t s);
 

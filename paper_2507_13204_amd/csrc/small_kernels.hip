@@ -41,14 +41,14 @@ k_mesh_small(MeshView m, MeshPass p, SmallPass sp) {
     // wave 0 (after the barrier) writes the partial, releases at device scope
     // and takes the counts.  The L2 write-back of its release covers the
     // whole workgroup's completed atomics.
-    if constexpr (has_rev(MODE)) __builtin_amdgcn_s_waitcnt(0);
+    if constexpr (is_atomic(MODE)) __builtin_amdgcn_s_waitcnt(0);
     double s = 0.0;
     if constexpr (has_sum(MODE)) s = block_sum_dyn(tsum, lds);
     __syncthreads();
     __shared__ int fin[kSmallMaxRanges];
     __shared__ int any_fin;
     int r0 = 0, nr = 0;
-    if constexpr (has_rev(MODE)) {
+    if constexpr (is_atomic(MODE)) {
         r0 = sp.wg_off[lb];
         nr = sp.wg_off[lb + 1] - r0;
     }
@@ -56,7 +56,7 @@ k_mesh_small(MeshView m, MeshPass p, SmallPass sp) {
         if constexpr (has_sum(MODE))
             if (threadIdx.x == 0) p.partials[lb] = s;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if constexpr (has_rev(MODE)) {
+        if constexpr (is_atomic(MODE)) {
             bool mine = false;
             if ((int)threadIdx.x < nr) {
                 const int r = sp.wg_list[r0 + threadIdx.x];
@@ -70,7 +70,7 @@ k_mesh_small(MeshView m, MeshPass p, SmallPass sp) {
             if (threadIdx.x == 0) last = atomicAdd(sp.ticket, 1) == (int)gridDim.x - 1;
     }
     __syncthreads();
-    if constexpr (has_rev(MODE)) {
+    if constexpr (is_atomic(MODE)) {
         if (any_fin) {
             // Last on some ranges: every scatter into them is visible after
             // wave 0's acquire (the caches it invalidates serve all waves).
@@ -131,6 +131,8 @@ hipError_t launch_small_mode(const MeshView& m, MeshMode mode, const MeshPass& p
         case M_PRIMAL: return launch_small_t<T, K, M_PRIMAL>(m, p, sp, s);
         case M_GRAD_ATOMIC: return launch_small_t<T, K, M_GRAD_ATOMIC>(m, p, sp, s);
         case M_ADJ_ATOMIC: return launch_small_t<T, K, M_ADJ_ATOMIC>(m, p, sp, s);
+        case M_HVP: return launch_small_t<T, K, M_HVP>(m, p, sp, s);
+        case M_JVP: return launch_small_t<T, K, M_JVP>(m, p, sp, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -156,8 +158,9 @@ bool mesh_small_eligible(const MeshView& m, int block) {
 hipError_t launch_mesh_small(const MeshView& m, MeshMode mode, const MeshPass& p,
                              const SmallPass& sp, hipStream_t s) {
     if (!mesh_small_eligible(m, p.block) || !sp.ticket) return hipErrorInvalidValue;
-    if (mode != M_PRIMAL && (!p.gacc || !sp.grad || !sp.range_done || !sp.range_need ||
-                             !sp.wg_off || !sp.wg_list))
+    const bool scatter = mode == M_GRAD_ATOMIC || mode == M_ADJ_ATOMIC || mode == M_HVP;
+    if (scatter && (!p.gacc || !sp.grad || !sp.range_done || !sp.range_need || !sp.wg_off ||
+                    !sp.wg_list))
         return hipErrorInvalidValue;
     return m.dtype == F64 ? launch_small_k<double>(m, mode, p, sp, s)
                           : launch_small_k<float>(m, mode, p, sp, s);

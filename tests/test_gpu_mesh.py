@@ -349,6 +349,16 @@ def test_one_launch_small_meshes(name, dtype):
     f2, g2 = multi.gradient(x)
     assert srel(f.item(), f2.item()) <= 1e-14
     assert rel(g.cpu().numpy(), g2.cpu().numpy()) <= tol_g
+    # HVP (a scatter like the gradient) and JVP (a sum like f), one launch each
+    d = inputs.fd_directions((m.n_nodes,), 1, seed=19)[0]
+    dd = to_dev(d, x.dtype)
+    mm = m if dtype == "f64" else m.astype(np.float32)
+    h_ref = oracle.mesh_hvp(m.n_nodes, m.conn, mm.B.astype(np.float64), mm.w.astype(np.float64),
+                            mm.x.astype(np.float64), dd.cpu().numpy().astype(np.float64))
+    for _ in range(2):
+        assert rel(one.hvp(x, dd).cpu().numpy().astype(np.float64), h_ref) <= tol_g
+        j1, j2 = one.jvp(x, dd).item(), multi.jvp(x, dd).item()
+        assert srel(j1, j2) <= (1e-12 if dtype == "f64" else TOL_F32)
     fbar = torch.tensor([0.75], dtype=torch.float64, device="cuda")
     for _ in range(2):
         _check(m, None, one.adjoint(x, fbar).cpu().numpy(), dtype, fbar=0.75)
