@@ -397,3 +397,28 @@ def test_f32_accumulation_buffer_is_clear_between_calls(adj):
     for _ in range(3):
         acc.gradient(x, out=base)
     assert rel(base.cpu().numpy().astype(np.float64), 3.0 * g_ref) <= TOL_F32
+
+
+def test_one_launch_repeated_on_a_full_grid():
+    """The largest one-launch mesh (64 workgroups, 16,384 nodes) with random
+    connectivity, so every workgroup counts itself done on all 32 node ranges:
+    300 gradient calls in a row, every result against the oracle (a lost or
+    late contribution would show as a large error in some call)."""
+    m = inputs.random_mesh(16384, 32768, 8, 41)
+    obj, x = _obj(m)
+    assert obj.workspace_bytes >= 8 * 16384
+    _, g_ref = _oracle_grad(m)
+    g = torch.empty_like(x)
+    f = torch.empty((), dtype=torch.float64, device="cuda")
+    worst = 0.0
+    outs = []
+    for i in range(300):
+        obj.gradient(x, out=g, f_out=f)
+        outs.append(g.clone())
+        if len(outs) == 50:
+            for o in outs:
+                worst = max(worst, rel(o.cpu().numpy(), g_ref))
+            outs = []
+    for o in outs:
+        worst = max(worst, rel(o.cpu().numpy(), g_ref))
+    assert worst <= TOL_F64_G, worst
