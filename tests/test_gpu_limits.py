@@ -40,7 +40,7 @@ def test_largest_incidence_count():
     assert rel(g, g_ref) <= TOL_F64_G
 
 
-@pytest.mark.parametrize("adj", ["atomic", "gather"])
+@pytest.mark.parametrize("adj", ["atomic", "gather", "tiled"])
 def test_largest_node_index(adj):
     """n_nodes = 2^31 - 1 with elements on nodes at both ends of the range,
     the last node included.  The oracle runs on the touched nodes renumbered
