@@ -174,7 +174,9 @@ pg_status pg_mesh_batch_plan(pg_plan* plan, int32_t n_inst, const pg_instance* i
  * neighbours' residuals and writes its own gradient entry: the reverse
  * threads rescheduled), or PG_ADJ_ATOMIC (the paper's schedule: every
  * residual scatters into three entries of df/dx with atomic adds).
- * x, b, gx, gb: n entries of the plan dtype. */
+ * x, b, gx, gb: n entries of the plan dtype.  For n <= 16,384 the last
+ * workgroup to finish reduces f (a ticket in the workspace, zero between
+ * calls), so the objective and the gather-form gradient are one launch each. */
 pg_status pg_laplace1d_plan(pg_plan* plan, int64_t n, pg_dtype dtype, const pg_options* opts,
                             size_t* workspace_bytes);
 pg_status pg_laplace1d_objective(pg_plan plan, const void* x, const void* b, double* f_out,
