@@ -340,7 +340,9 @@ typedef struct {
  * intermediates in registers and recompute them in the reverse pass (no
  * tape); a gather read only by one group runs inside it, its reverse being
  * an LDS-combined atomic scatter; the group holding the sum runs its
- * forward and reverse in one pass (the seed of f is the constant 1).  The
+ * forward and reverse in one pass (the seed of f is the constant 1), and
+ * when the summed view has at most 16,384 entries its last workgroup, found
+ * by a ticket in the workspace, reduces f (no separate reduction launch).  The
  * conclusion of the paper names kernel fusion and recomputation as ways to
  * cut the cost of the generated gradient.  0: one kernel per construct each
  * way (the sum's partials are taken by the kernel producing the summed
