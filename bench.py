@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--scatter", type=int, default=0, help="0 combine in LDS, 1 direct atomics")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 keys of the hex line")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-vs-per-instance keys of the hex line")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--workload", default="hex",
                     choices=["hex", "dense", "bdense", "batch", "chain", "paper", "program"],
@@ -100,22 +103,55 @@ def traffic_record(kernel_key: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(m, budget_s: float, gbytes: float):
+def host_cpu():
+    """The host's CPU model (/proc/cpuinfo) and its core counts."""
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"model": model, "nproc": avail, "os_cpu_count": os.cpu_count()}
+
+
+def _median_runs(fn, budget_s: float):
     import numpy as np
-    import oracle
     times = []
     t_end = time.perf_counter() + budget_s
     while True:
         t0 = time.perf_counter()
-        oracle.mesh_gradient(m.n_nodes, m.conn, m.B, m.w, m.x)
+        r = fn()
         times.append(time.perf_counter() - t0)
         if time.perf_counter() > t_end and len(times) >= 3:
             break
-    med = float(np.median(times))
-    return {"value": round(gbytes / med, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"full {m.name} FP64 gradient (f and grad), single-threaded C oracle, "
-                      f"median of {len(times)} runs = {med * 1e3:.1f} ms",
-            "cpu": platform.processor() or platform.machine()}
+    return float(np.median(times)), len(times), r
+
+
+def cpu_baseline(m, budget_s: float, gbytes: float):
+    """The oracle's FP64 gradient of the whole mesh on the host: the OpenMP
+    build on every core the process may use (the reported value) and the
+    plain single-threaded build, each for half the budget."""
+    import oracle
+    med1, n1, _ = _median_runs(lambda: oracle.mesh_gradient(m.n_nodes, m.conn, m.B, m.w, m.x),
+                               budget_s / 2)
+    medT, nT, r = _median_runs(
+        lambda: oracle.mesh_gradient_threads(m.n_nodes, m.conn, m.B, m.w, m.x), budget_s / 2)
+    threads = r[2]
+    cpu = host_cpu()
+    return {"value": round(gbytes / medT, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": f"full {m.name} FP64 gradient (f and grad), C oracle built with OpenMP on "
+                      f"{threads} threads (per-thread partials combined in thread order), "
+                      f"median of {nT} runs = {medT * 1e3:.1f} ms",
+            "single_thread": {"value": round(gbytes / med1, 3), "unit": "GB/s", "cores": 1,
+                              "sample": f"plain C oracle, median of {n1} runs = {med1 * 1e3:.1f} ms"},
+            "cpu": cpu["model"], "nproc": cpu["nproc"], "os_cpu_count": cpu["os_cpu_count"]}
 
 
 def bench_hex(args):
@@ -224,57 +260,208 @@ def bench_hex(args):
     out["hvp_ms"] = round(_timed(lambda: obj0.hvp(x0, dvec, out=hv), 20, 3), 5)
     out["jvp_ms"] = round(_timed(lambda: obj0.jvp(x0, dvec), 20, 3), 5)
 
-    # the autograd form: forward = objective, backward = adjoint seeded with
-    # grad_output, for recompute and store checkpointing (host autograd
-    # overhead included, as a user of the Function sees it)
-    from paper_2507_13204_amd import MeshFn
-    ag = {}
-    for ck in ("recompute", "store"):
-        oa = MeshObjective(conn, B, w, m.n_nodes, ckpt=ck)
-        xa = x.detach().clone().requires_grad_(True)
+    if args.dtype == "f64":
+        import oracle
+        f0, g0 = copies[0][0].gradient(copies[0][1])
+        f_ref, g_ref = oracle.mesh_gradient(m.n_nodes, m.conn, m.B, m.w, m.x)
+        gh = g0.cpu().numpy()
+        out["error_vs_oracle"] = {
+            "f": abs(f0.item() - f_ref) / abs(f_ref),
+            "grad": float(np.linalg.norm(gh - g_ref) / np.linalg.norm(g_ref))}
+    _progress("headline done")
 
-        def fwd():
-            with torch.no_grad():
-                MeshFn.apply(xa, oa)
-
-        def fwd_bwd():
-            xa.grad = None
-            MeshFn.apply(xa, oa).backward()
-
-        t_f = _timed(fwd, 20, 3)
-        t_fb = _timed(fwd_bwd, 20, 3)
-        ag[ck] = {"forward_ms": round(t_f, 5), "forward_backward_ms": round(t_fb, 5),
-                  "fwd_plus_bwd_over_fwd": round(t_fb / t_f, 4), "cache": "warm"}
-        oa.close()
-    out["autograd"] = ag
-
+    ccs = [(obj.conn, obj.B, obj.w, xx) for obj, xx, _, _ in copies]
+    out["autograd"] = _hex_autograd(args, m, ccs)
+    _progress("autograd done")
     if not args.no_variants:
-        variants = {}
-        for adj in ("atomic", "gather", "colour", "tiled"):
-            if adj == args.adjoint:
-                continue
-            o2 = MeshObjective(conn, B, w, m.n_nodes, adjoint=adj)
-            g2 = torch.empty_like(x)
-            for _ in range(3):
-                o2.gradient(x, out=g2)
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(20):
-                o2.gradient(x, out=g2)
-            e1.record()
-            torch.cuda.synchronize()
-            vms = e0.elapsed_time(e1) / 20
-            variants[adj] = {"ms": round(vms, 5), "GBps_algorithmic": round(gbytes / (vms * 1e-3), 2),
-                             "over_objective": round(vms / ms_obj, 4), "cache": "warm"}
-            o2.close()
-        out["variants"] = variants
-
+        out["variants"] = _hex_variants(args, m, ccs, gbytes, ms_obj)
+        _progress("variants done")
+    if args.dtype == "f64" and not args.no_fp32:
+        out["fp32"] = _hex_fp32(args, m)
+        _progress("fp32 done")
+    if not args.no_batch:
+        out["batch"] = _batch_vs_per_instance(args)
+        _progress("batch done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(m, args.cpu_seconds, gbytes)
 
     print(json.dumps(out), flush=True)
+
+
+def _progress(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _rotating(fn, n_copies, steps, warmup):
+    """ms per step of fn(i) over copies i mod n_copies, back to back."""
+    import torch
+    for i in range(warmup):
+        fn(i % n_copies)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for i in range(steps):
+        fn(i % n_copies)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def _hex_autograd(args, m, ccs):
+    """The autograd form on the rotating copies, for each policy of what the
+    forward keeps: forward (grad mode off: the objective alone), forward with
+    the gradient requested, and forward + backward, as a user of MeshFn sees
+    them (host autograd overhead included)."""
+    import torch
+    from paper_2507_13204_amd import MeshFn, MeshObjective
+    res = {}
+    for pol in ("gradient", "store", "recompute"):
+        objs = [MeshObjective(c, B, w, m.n_nodes, autograd=pol) for c, B, w, _ in ccs]
+        xs = [x.detach().clone().requires_grad_(True) for *_, x in ccs]
+
+        def fwd_nograd(i):
+            with torch.no_grad():
+                MeshFn.apply(xs[i], objs[i])
+
+        def fwd(i):
+            MeshFn.apply(xs[i], objs[i])
+
+        def fwd_bwd(i):
+            xs[i].grad = None
+            MeshFn.apply(xs[i], objs[i]).backward()
+
+        t0 = _rotating(fwd_nograd, len(objs), args.steps, 3)
+        t1 = _rotating(fwd, len(objs), args.steps, 3)
+        t2 = _rotating(fwd_bwd, len(objs), args.steps, 3)
+        res[pol] = {"forward_nograd_ms": round(t0, 5), "forward_ms": round(t1, 5),
+                    "forward_backward_ms": round(t2, 5),
+                    "fwd_plus_bwd_over_fwd": round(t2 / t1, 4),
+                    "fwd_plus_bwd_over_objective": round(t2 / t0, 4),
+                    "cache": f"cold ({len(objs)} rotating copies)"}
+        for o in objs:
+            o.close()
+    auto = MeshObjective(*ccs[0][:3], m.n_nodes)
+    res["auto_policy"] = auto.autograd_policy
+    auto.close()
+    return res
+
+
+def _hex_variants(args, m, ccs, gbytes, ms_obj):
+    """The deterministic adjoint schedules on the rotating copies."""
+    from paper_2507_13204_amd import MeshObjective
+    import torch
+    res = {}
+    for adj in ("atomic", "gather", "colour", "tiled"):
+        if adj == args.adjoint:
+            continue
+        objs = [MeshObjective(c, B, w, m.n_nodes, adjoint=adj) for c, B, w, _ in ccs]
+        gs = [torch.empty_like(x) for *_, x in ccs]
+        vms = _rotating(lambda i: objs[i].gradient(ccs[i][3], out=gs[i]), len(objs), args.steps, 3)
+        res[adj] = {"ms": round(vms, 5), "GBps_algorithmic": round(gbytes / (vms * 1e-3), 2),
+                    "over_objective": round(vms / ms_obj, 4),
+                    "cache": f"cold ({len(objs)} rotating copies)"}
+        for o in objs:
+            o.close()
+    return res
+
+
+def _hex_fp32(args, m):
+    """FP32 storage (x, B, w, grad), every accumulation FP64: time on rotating
+    copies, algorithmic GB/s, and the error against the oracle run on the
+    FP32-rounded inputs (the acceptance bar, 1e-5) and on the FP64 inputs."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2507_13204_amd import MeshObjective
+    dev = torch.device("cuda:0")
+    conn = torch.from_numpy(m.conn).to(dev)
+    B = torch.from_numpy(m.B).to(dev, torch.float32)
+    w = torch.from_numpy(m.w).to(dev, torch.float32)
+    x = torch.from_numpy(m.x).to(dev, torch.float32)
+    cps = []
+    for c in range(max(1, args.copies)):
+        cc = (conn, B, w, x) if c == 0 else tuple(t.clone() for t in (conn, B, w, x))
+        cps.append((MeshObjective(cc[0], cc[1], cc[2], m.n_nodes), cc[3], torch.empty_like(cc[3])))
+    torch.cuda.synchronize()
+    ms_g = _rotating(lambda i: cps[i][0].gradient(cps[i][1], out=cps[i][2]), len(cps),
+                     args.steps, args.warmup)
+    ms_f = _rotating(lambda i: cps[i][0].objective(cps[i][1]), len(cps), args.steps, args.warmup)
+    for o, *_ in cps:
+        o.timing(1)
+    for i in range(args.steps):
+        cps[i % len(cps)][0].gradient(cps[i % len(cps)][1], out=cps[i % len(cps)][2])
+    torch.cuda.synchronize()
+    kms, kn = 0.0, 0
+    for o, *_ in cps:
+        a, b = o.timing_read()
+        o.timing(0)
+        kms, kn = kms + a, kn + b
+    kms /= max(kn, 1)
+    f, g = cps[0][0].gradient(cps[0][1])
+    gh = g.cpu().numpy().astype(np.float64)
+    m32 = m.astype(np.float32)
+    f_r, g_r = oracle.mesh_gradient(m.n_nodes, m.conn, m32.B.astype(np.float64),
+                                    m32.w.astype(np.float64), m32.x.astype(np.float64))
+    f_64, g_64 = oracle.mesh_gradient(m.n_nodes, m.conn, m.B, m.w, m.x)
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    gb = algorithmic_bytes(m.n_nodes, m.n_elems, 8, 4, True) / 1e9
+    return {"gradient_ms": round(ms_g, 5), "objective_ms": round(ms_f, 5),
+            "GBps": round(gb / (ms_g * 1e-3), 2), "pct_hbm_peak": round(100 * gb / (ms_g * 1e-3) / PEAK_HBM_GBS, 2),
+            "gradient_over_objective": round(ms_g / ms_f, 4),
+            "kernel_ms": round(kms, 5), "kernel_GBps": round(gb / (kms * 1e-3), 2),
+            "algorithmic_bytes": int(gb * 1e9),
+            "error_vs_rounded_input_oracle": {"f": abs(f.item() - f_r) / abs(f_r), "grad": rel(gh, g_r)},
+            "error_vs_fp64_input_oracle": {"f": abs(f.item() - f_64) / abs(f_64), "grad": rel(gh, g_64)},
+            "cache": f"cold ({len(cps)} rotating copies)"}
+
+
+def _batch_vs_per_instance(args):
+    """256 uneven hex meshes: the one-launch batched gradient against 256
+    per-instance gradient calls on the same GPU, same inputs."""
+    import torch
+    from paper_2507_13204_amd import MeshBatch, MeshObjective, inputs
+    bt = inputs.uneven_batch(args.batch_n)
+    dev = torch.device("cuda:0")
+    conn = torch.from_numpy(bt.conn).to(dev)
+    B = torch.from_numpy(bt.B).to(dev)
+    w = torch.from_numpy(bt.w).to(dev)
+    x = torch.from_numpy(bt.x).to(dev)
+    N, E = int(bt.x.shape[0]), int(bt.conn.shape[0])
+    gbytes = algorithmic_bytes(N, E, 8, 8, True) / 1e9
+    g = torch.empty_like(x)
+    f = torch.empty(bt.n_inst, dtype=torch.float64, device=dev)
+    ob = MeshBatch(bt.inst, conn, B, w)
+    ms_b = _timed(lambda: ob.gradient(x, out=g, f_out=f), args.steps, args.warmup)
+    k_ms = _hook_ms(ob, lambda: ob.gradient(x, out=g, f_out=f), args.steps)
+    ob.close()
+    plans = []
+    for i in range(bt.n_inst):
+        nn, ne, no, eo = (int(v) for v in bt.inst[i])
+        plans.append((MeshObjective(conn[eo:eo + ne], B[eo:eo + ne], w[eo:eo + ne], nn),
+                      x[no:no + nn], g[no:no + nn], f[i:i + 1].view(())))
+
+    def per_instance():
+        for p, xi, gi, fi in plans:
+            p.gradient(xi, out=gi, f_out=fi)
+
+    ms_pi = _timed(per_instance, max(3, args.steps // 4), 1)
+    for p, *_ in plans:
+        p.close()
+    return {"workload": f"{bt.n_inst} hex meshes, sides log-uniform in [10,100], {N} nodes, "
+                        f"{E} elements, FP64 gradient, atomic adjoint",
+            "batched_ms": round(ms_b, 4), "batched_instances_per_s": round(bt.n_inst / (ms_b * 1e-3), 1),
+            "batched_GBps": round(gbytes / (ms_b * 1e-3), 2),
+            "batched_kernel_ms": round(k_ms, 4),
+            "batched_kernel_frac_hbm_peak": round(gbytes / (k_ms * 1e-3) / PEAK_HBM_GBS, 4),
+            "per_instance_ms": round(ms_pi, 4),
+            "per_instance_instances_per_s": round(bt.n_inst / (ms_pi * 1e-3), 1),
+            "per_instance_GBps": round(gbytes / (ms_pi * 1e-3), 2),
+            "batched_over_per_instance_speedup": round(ms_pi / ms_b, 3),
+            "algorithmic_bytes": int(gbytes * 1e9)}
 
 
 def _timed(fn, steps, warmup):

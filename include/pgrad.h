@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define PGRAD_VERSION 1
+#define PGRAD_VERSION 2
 #define PG_MAX_K 32           /* maximum nodes per element */
 #define PG_WORKSPACE_ALIGN 256 /* required alignment of the workspace */
 
@@ -64,7 +64,8 @@ typedef enum {
     PG_EWORKSPACE = 5,   /* workspace missing, too small or misaligned */
     PG_EHIP = 6,         /* a HIP runtime call or launch failed */
     PG_EUNSUPPORTED = 7, /* valid request this plan kind does not offer */
-    PG_ESTATE = 8        /* plan used before pg_bind_workspace, or no tape stored */
+    PG_ESTATE = 8        /* plan used before pg_bind_workspace, or no stored
+                            forward values for this x (see pg_adjoint) */
 } pg_status;
 
 typedef enum { PG_F64 = 0, PG_F32 = 1 } pg_dtype;
@@ -89,10 +90,17 @@ typedef enum {
 } pg_adjoint_kind;
 
 /* What the forward pass keeps for the reverse pass (section 4: intermediates
- * are recorded in views between kernels). */
+ * are recorded in views between kernels; the conclusion: a tape whose size is
+ * deduced once, outside the kernels). */
 typedef enum {
     PG_RECOMPUTE = 0, /* the reverse pass recomputes the gathered values */
-    PG_STORE = 1      /* pg_objective stores them in the workspace */
+    PG_STORE = 1,     /* pg_objective stores them in the workspace */
+    PG_CKPT_AUTO = 2  /* chosen by memory when the plan is made: PG_STORE if
+                         one call's tape (pg_tape_bytes) fits
+                         options.tape_budget bytes, else PG_RECOMPUTE.  A
+                         budget of 0 means a quarter of the device memory
+                         that hipMemGetInfo reports free at that moment.
+                         pg_plan_info reports the choice. */
 } pg_ckpt;
 
 typedef struct {
@@ -118,6 +126,9 @@ typedef struct {
                            workspace buffer and the last workgroup to finish
                            writes grad from it, clears it and sums f), 1 = the
                            multi-launch path at every size */
+    int32_t reserved;   /* must be 0 */
+    int64_t tape_budget; /* PG_CKPT_AUTO: bytes the stored tape may take
+                            (0: a quarter of the free device memory) */
 } pg_options;
 
 /* One instance of a mesh batch: its nodes are x[node_off .. node_off+n_nodes)
@@ -212,11 +223,88 @@ pg_status pg_objective(pg_plan plan, const void* x, double* f_out, pg_stream str
 pg_status pg_gradient(pg_plan plan, const void* x, void* grad, double* f_out, pg_stream stream);
 
 /* Reverse pass only, seeded with fbar (device FP64, 1 entry or n_inst):
- * grad = fbar * df/dx.  With ckpt == PG_STORE it reads the values stored by
- * the last pg_objective on the same x (PG_ESTATE if none was stored);
- * with PG_RECOMPUTE it recomputes them from x. */
+ * grad = fbar * df/dx.  With ckpt == PG_STORE it reads the values the last
+ * pg_objective stored in the workspace, and returns PG_ESTATE (nothing
+ * enqueued) unless that call was made with the same x pointer and no later
+ * call has overwritten them (a batched-dense pg_gradient or recomputing
+ * adjoint reuses that buffer).  The caller must not have changed the
+ * contents of x in between: the library compares pointers, not values.
+ * With PG_RECOMPUTE it recomputes them from x. */
 pg_status pg_adjoint(pg_plan plan, const void* x, const double* fbar, void* grad,
                      pg_stream stream);
+
+/* ----------------------------------------------- per-call tape (section 4)
+ *
+ * The paper's generated gradient records the forward values its reverse pass
+ * reads in views made for that call.  These calls do the same with a tape
+ * the caller owns, so any number of forward passes can be outstanding on one
+ * plan (the backward of an autograd function keeps its own tape), whatever
+ * the plan's ckpt option.  What a tape holds:
+ *   mesh and mesh batch: u_e = sum_j B[e,j] x[conn[e,j]] for every element,
+ *     FP64 (n_elems entries; a batch's concatenated elements);
+ *   batched dense: V = W (.) psi'(A X), m x n in the plan dtype.
+ * Dense plans and the section 4 example have no tape (PG_EUNSUPPORTED).
+ * tape: device memory of pg_tape_bytes bytes, 16-byte aligned, not
+ * overlapping any operand, output or the workspace. */
+pg_status pg_tape_bytes(pg_plan plan, size_t* bytes);
+/* f_out = f(x) as pg_objective, and the forward values written to tape. */
+pg_status pg_objective_tape(pg_plan plan, const void* x, double* f_out, void* tape,
+                            pg_stream stream);
+/* grad = fbar * df/dx from the forward values in tape (written by
+ * pg_objective_tape of this plan); x is not read. */
+pg_status pg_adjoint_tape(pg_plan plan, const double* fbar, const void* tape, void* grad,
+                          pg_stream stream);
+
+/* y[i] = alpha[0] * x[i] for i < n, evaluated in FP64 and rounded once to
+ * dtype; y may equal x.  alpha: device FP64.  The seed of a scalar objective
+ * (section 3.2: the adjoint of the sum broadcasts the seed) applied to a
+ * gradient formed with seed 1, as when f and its gradient are computed in
+ * one forward call and the backward of an autograd function receives
+ * grad_output afterwards. */
+pg_status pg_scale(pg_dtype dtype, int64_t n, const double* alpha, const void* x, void* y,
+                   pg_stream stream);
+
+/* ------------------------------------------------------------ plan queries */
+
+typedef struct {
+    int32_t kind;          /* 1 mesh, 2 dense, 3 batched dense, 4 mesh batch, 5 section 4 example */
+    int32_t dtype;         /* pg_dtype */
+    int32_t adjoint;       /* resolved pg_adjoint_kind (never PG_ADJ_AUTO) */
+    int32_t ckpt;          /* resolved pg_ckpt (never PG_CKPT_AUTO) */
+    int32_t block;         /* threads per workgroup of the element pass */
+    int32_t tile;          /* elements per thread */
+    int32_t lds_slots;     /* LDS table of the combined atomic scatter (0: none; set at bind) */
+    int32_t one_launch;    /* 1 if every call is one launch */
+    int32_t n_colours;     /* colour classes (colour adjoint, after bind), else 0 */
+    int32_t bound;         /* 1 after a successful pg_bind_workspace */
+    int64_t workspace_bytes;
+    int64_t tape_bytes;    /* pg_tape_bytes */
+    int64_t tape_budget;   /* the budget PG_CKPT_AUTO compared against (0 if not AUTO) */
+} pg_plan_info_t;
+pg_status pg_plan_info(pg_plan plan, pg_plan_info_t* info);
+
+/* Copy one integer structure of a bound mesh plan to host memory, so that it
+ * can be compared with an independent construction (the conclusion's
+ * rescheduled reverse threads need them exact):
+ *   PG_EXPORT_CSR_OFFS    int32[n_nodes + 1]: row offsets of the transposed
+ *                         connectivity (gather adjoint);
+ *   PG_EXPORT_CSR_INC     int32[n_elems * k]: per node, its incidences
+ *                         e * k + j with conn[e,j] == node, ascending;
+ *   PG_EXPORT_COLOUR_OFFS int64[n_colours + 1]: class c is entries
+ *                         [offs[c], offs[c+1]) of the element list;
+ *   PG_EXPORT_COLOUR_ELEMS int32[n_elems]: elements, class by class,
+ *                         ascending inside a class (colour adjoint).
+ * host_dst NULL: only *bytes (host, out) is set.  Otherwise capacity must be
+ * at least that size.  Waits for the plan's last bind (a device-to-host copy
+ * on the null stream).  PG_EUNSUPPORTED if the plan has no such structure. */
+typedef enum {
+    PG_EXPORT_CSR_OFFS = 0,
+    PG_EXPORT_CSR_INC = 1,
+    PG_EXPORT_COLOUR_OFFS = 2,
+    PG_EXPORT_COLOUR_ELEMS = 3
+} pg_export_what;
+pg_status pg_plan_export(pg_plan plan, int32_t what, void* host_dst, size_t capacity,
+                         size_t* bytes);
 
 /* Hessian-vector product of the mesh objective (tangent over reverse,
  * named as future work in the conclusion):

@@ -36,6 +36,32 @@ def build(force: bool = True) -> str:
 
 
 _lib = None
+_lib_omp = None
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+
+
+def build_omp(force: bool = True) -> str:
+    """The same source built with OpenMP (-DORC_OMP): adds the threaded mesh
+    gradient used to time the oracle on every host core."""
+    if force or not os.path.exists(_LIB_OMP) or os.path.getmtime(_LIB_OMP) < os.path.getmtime(_SRC):
+        tmp = _LIB_OMP + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-fopenmp",
+                               "-DORC_OMP", "-std=c11", "-Wall", "-Wextra", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_OMP)
+    return _LIB_OMP
+
+
+def lib_omp():
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_LIB_OMP) or os.path.getmtime(_LIB_OMP) < os.path.getmtime(_SRC):
+            build_omp(force=True)
+        L = ctypes.CDLL(_LIB_OMP)
+        L.orc_mesh_gradient_threads.argtypes = [_I64, _I64, _I32, _i32, _d, _d, _d, ctypes.c_double,
+                                                _d, _d]
+        L.orc_mesh_gradient_threads.restype = ctypes.c_int
+        _lib_omp = L
+    return _lib_omp
 
 _d = ctypes.POINTER(ctypes.c_double)
 _i32 = ctypes.POINTER(ctypes.c_int32)
@@ -63,6 +89,8 @@ def lib():
         L.orc_mesh_csr.argtypes = [_I64, _I64, _I32, _i32, _i32, _i32]
         L.orc_colour_conflicts.argtypes = [_I64, _I64, _I32, _i32, _i32, _I32]
         L.orc_colour_conflicts.restype = ctypes.c_int64
+        L.orc_greedy_colour.argtypes = [_I64, _I64, _I32, _i32, _I32, _i32]
+        L.orc_greedy_colour.restype = ctypes.c_int32
         L.orc_dense_objective.argtypes = [_I64, _I64, _d, _d, _d, _d, _d]
         L.orc_dense_gradient.argtypes = [_I64, _I64, _d, _d, _d, ctypes.c_double, _d, _d]
         L.orc_bdense_columns.argtypes = [_I64, _I64, _d, _d, _d, _I64, _i64p, _d, _d]
@@ -191,6 +219,20 @@ def mesh_gradient(n_nodes, conn, B, w, x, fbar: float = 1.0) -> Tuple[float, np.
     return float(f[0]), g
 
 
+def mesh_gradient_threads(n_nodes, conn, B, w, x, fbar: float = 1.0) -> Tuple[float, np.ndarray, int]:
+    """mesh_gradient with its loops on every host thread (OpenMP build):
+    (f, grad, threads used).  For timing the oracle on the host's cores."""
+    N, E, k, conn, B = _mesh_args(n_nodes, conn, B)
+    w, x = _f64(w), _f64(x)
+    g = np.empty(N)
+    f = ctypes.c_double()
+    t = lib_omp().orc_mesh_gradient_threads(N, E, k, _p(conn, _i32), _p(B), _p(w), _p(x),
+                                             float(fbar), ctypes.byref(f), _p(g))
+    if t < 0:
+        raise OracleError(-t, "mesh_gradient_threads")
+    return f.value, g, int(t)
+
+
 def mesh_hvp(n_nodes, conn, B, w, x, d) -> np.ndarray:
     N, E, k, conn, B = _mesh_args(n_nodes, conn, B)
     w, x, d = _f64(w), _f64(x), _f64(d)
@@ -207,6 +249,19 @@ def mesh_csr(n_nodes, conn) -> Tuple[np.ndarray, np.ndarray]:
     _chk(lib().orc_mesh_csr(int(n_nodes), E, k, _p(conn, _i32), _p(offs, _i32), _p(inc, _i32)),
          "csr")
     return offs, inc
+
+
+def greedy_colour(n_nodes, conn, max_colours: int = 64) -> Tuple[np.ndarray, int]:
+    """Greedy colouring in element order (smallest colour no earlier element
+    sharing a node has); returns (colour per element, number of colours)."""
+    conn = _i32a(conn)
+    E, k = conn.shape
+    colour = np.zeros(E, dtype=np.int32)
+    nc = int(lib().orc_greedy_colour(int(n_nodes), E, k, _p(conn, _i32), int(max_colours),
+                                     _p(colour, _i32)))
+    if nc < 0:
+        raise OracleError(EINVAL, "greedy_colour")
+    return colour, nc
 
 
 def colour_conflicts(n_nodes, conn, colour, n_colours: int) -> int:

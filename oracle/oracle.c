@@ -232,6 +232,76 @@ int orc_mesh_gradient(int64_t N, int64_t E, int32_t k, const int32_t* conn, cons
     return ORC_OK;
 }
 
+#ifdef ORC_OMP
+#include <omp.h>
+
+/* The same gradient with its loops spread over the host's threads (built
+ * only as liboracle_omp.so, with -fopenmp -DORC_OMP; the CPU-baseline
+ * timing uses it, the parity tests use the plain build).  Thread t takes a
+ * contiguous block of elements in every loop; f is a Neumaier sum per
+ * thread, and the partial sums are added in thread order; each thread
+ * scatters into a private zeroed copy of g, and the copies are added node
+ * by node in thread order.  Returns the number of threads used, or a
+ * negative status. */
+int orc_mesh_gradient_threads(int64_t N, int64_t E, int32_t k, const int32_t* conn,
+                              const double* B, const double* w, const double* x, double fbar,
+                              double* f_out, double* g) {
+    int st = orc_mesh_check(N, E, k, conn);
+    if (st) return -st;
+    const int T = omp_get_max_threads();
+    double* u = (double*)malloc(sizeof(double) * (size_t)(E > 0 ? E : 1));
+    double* gt = (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1) * (size_t)T);
+    nsum_t* part = (nsum_t*)malloc(sizeof(nsum_t) * (size_t)T);
+    if (!u || !gt || !part) {
+        free(u);
+        free(gt);
+        free(part);
+        return -ORC_EINVAL;
+    }
+#pragma omp parallel num_threads(T)
+    {
+        const int t = omp_get_thread_num();
+        const int64_t e0 = E * t / T, e1 = E * (t + 1) / T;
+        nsum_t acc = {0.0, 0.0};
+        for (int64_t e = e0; e < e1; ++e) {
+            double a = 0.0;
+            for (int32_t j = 0; j < k; ++j) {
+                double prod = B[e * k + j] * x[conn[e * k + j]];
+                a = a + prod;
+            }
+            u[e] = a;
+            nsum_add(&acc, w[e] * psi(a));
+        }
+        part[t] = acc;
+        double* gl = gt + (size_t)N * (size_t)t;
+        for (int64_t i = 0; i < N; ++i) gl[i] = 0.0;
+        for (int64_t e = e0; e < e1; ++e) {
+            double v = fbar * w[e] * dpsi(u[e]);
+            for (int32_t j = 0; j < k; ++j) gl[conn[e * k + j]] += v * B[e * k + j];
+        }
+#pragma omp barrier
+        const int64_t n0 = N * t / T, n1 = N * (t + 1) / T;
+        for (int64_t i = n0; i < n1; ++i) {
+            double s = 0.0;
+            for (int q = 0; q < T; ++q) s += gt[(size_t)N * (size_t)q + (size_t)i];
+            g[i] = s;
+        }
+    }
+    if (f_out) {
+        nsum_t acc = {0.0, 0.0};
+        for (int t = 0; t < T; ++t) {
+            nsum_add(&acc, part[t].s);
+            nsum_add(&acc, part[t].c);
+        }
+        *f_out = nsum_get(&acc);
+    }
+    free(u);
+    free(gt);
+    free(part);
+    return T;
+}
+#endif
+
 /* Hessian-vector product of the mesh objective:
  * H d = G^T ( w (.) psi''(G x) (.) (G d) ). */
 int orc_mesh_hvp(int64_t N, int64_t E, int32_t k, const int32_t* conn, const double* B,
@@ -294,6 +364,52 @@ int64_t orc_colour_conflicts(int64_t N, int64_t E, int32_t k, const int32_t* con
     }
     free(last);
     return conflicts;
+}
+
+/* Greedy colouring in element order, from its definition: element e takes
+ * the smallest colour that no earlier element sharing a node with it has
+ * (e' < e with conn[e', i] == conn[e, j] for some i, j).  The elements that
+ * share a node with e are found through the transposed connectivity
+ * (orc_mesh_csr).  colour[E] is written; returns the number of colours, or
+ * -1 on bad arguments or if more than max_colours are needed.  Used to
+ * check, exactly, the colour classes the library builds for its non-atomic
+ * reverse scatter (the conclusion's rescheduled reverse threads). */
+int32_t orc_greedy_colour(int64_t N, int64_t E, int32_t k, const int32_t* conn, int32_t max_colours,
+                          int32_t* colour) {
+    if (orc_mesh_check(N, E, k, conn) != ORC_OK || max_colours <= 0) return -1;
+    int32_t* offs = (int32_t*)malloc(sizeof(int32_t) * (size_t)(N + 1));
+    int32_t* inc = (int32_t*)malloc(sizeof(int32_t) * (size_t)(E * k > 0 ? E * k : 1));
+    char* taken = (char*)malloc((size_t)max_colours);
+    if (!offs || !inc || !taken) {
+        free(offs);
+        free(inc);
+        free(taken);
+        return -1;
+    }
+    orc_mesh_csr(N, E, k, conn, offs, inc);
+    int32_t n_colours = 0;
+    for (int64_t e = 0; e < E; ++e) {
+        memset(taken, 0, (size_t)max_colours);
+        for (int32_t j = 0; j < k; ++j) {
+            int32_t n = conn[e * k + j];
+            for (int32_t q = offs[n]; q < offs[n + 1]; ++q) {
+                int64_t other = inc[q] / k; /* incidence e' * k + i */
+                if (other < e) taken[colour[other]] = 1;
+            }
+        }
+        int32_t c = 0;
+        while (c < max_colours && taken[c]) ++c;
+        if (c == max_colours) {
+            n_colours = -1;
+            break;
+        }
+        colour[e] = c;
+        if (c + 1 > n_colours) n_colours = c + 1;
+    }
+    free(offs);
+    free(inc);
+    free(taken);
+    return n_colours;
 }
 
 /* ------------------------------------------------------------------ dense */

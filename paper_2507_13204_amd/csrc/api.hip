@@ -188,6 +188,8 @@ struct pg_plan_s {
     bool bound = false;
     bool tape_valid = false;
     const void* tape_x = nullptr;
+    size_t tape_bytes = 0;      // one call's tape (pg_tape_bytes)
+    int64_t tape_budget = 0;    // what PG_CKPT_AUTO compared it against
     // measurement hook
     int32_t timing_mode = 0;
     std::vector<hipEvent_t> ev;  // pairs: ev[2i] start, ev[2i+1] stop
@@ -223,8 +225,10 @@ pg_status check_opts(const pg_options* o, pg_options* out) {
     if (out->adjoint < PG_ADJ_AUTO || out->adjoint > PG_ADJ_TILED)
         return fail(PG_EINVAL, "options.adjoint %d is not a pg_adjoint_kind", out->adjoint);
     if (out->adjoint == PG_ADJ_AUTO) out->adjoint = PG_ADJ_ATOMIC;
-    if (out->ckpt != PG_RECOMPUTE && out->ckpt != PG_STORE)
+    if (out->ckpt != PG_RECOMPUTE && out->ckpt != PG_STORE && out->ckpt != PG_CKPT_AUTO)
         return fail(PG_EINVAL, "options.ckpt %d is not a pg_ckpt", out->ckpt);
+    if (out->reserved != 0) return fail(PG_EINVAL, "options.reserved must be 0");
+    if (out->tape_budget < 0) return fail(PG_EINVAL, "options.tape_budget must be >= 0");
     if (out->block == 0) out->block = kDefaultBlock;
     if (out->block < 64 || out->block > 1024 || out->block % 64)
         return fail(PG_EINVAL, "options.block %d must be a multiple of 64 in [64, 1024]",
@@ -255,6 +259,29 @@ pg_plan_s* new_plan(Kind kind, pg_dtype dt, const pg_options& o) {
     p->dtype = dt;
     p->opt = o;
     return p;
+}
+
+// PG_CKPT_AUTO: store the tape when one call's tape fits the budget (the
+// caller's, or a quarter of the free device memory now), else recompute.
+pg_status resolve_ckpt(pg_plan_s* p, size_t tape_bytes) {
+    p->tape_bytes = tape_bytes;
+    if (p->opt.ckpt != PG_CKPT_AUTO) return PG_OK;
+    int64_t budget = p->opt.tape_budget;
+    if (budget == 0) {
+        size_t free_b = 0, total_b = 0;
+        hipError_t e = hipMemGetInfo(&free_b, &total_b);
+        if (e != hipSuccess) return fail(PG_EHIP, "hipMemGetInfo: %s", hipGetErrorString(e));
+        budget = (int64_t)(free_b / 4);
+    }
+    p->tape_budget = budget;
+    p->opt.ckpt = (tape_bytes > 0 && (int64_t)tape_bytes <= budget) ? PG_STORE : PG_RECOMPUTE;
+    return PG_OK;
+}
+
+// Frees a plan that failed before it was handed to the caller.
+pg_status drop_plan(pg_plan_s* p, pg_status st) {
+    delete p;
+    return st;
 }
 
 constexpr int kMaxColours = 64;
@@ -470,6 +497,14 @@ pg_status check_out_alias(pg_plan p, const void* out, size_t out_bytes, const vo
     return PG_OK;
 }
 
+pg_status check_tape(pg_plan p, const void* tape, const void* x) {
+    if (p->kind != K_MESH && p->kind != K_BATCH && p->kind != K_BDENSE)
+        return fail(PG_EUNSUPPORTED, "this plan kind records no tape");
+    if (!tape && p->tape_bytes > 0) return fail(PG_EINVAL, "tape is NULL");
+    if ((uintptr_t)tape % 16) return fail(PG_EINVAL, "tape must be 16-byte aligned");
+    return check_out_alias(p, tape, p->tape_bytes, x, "tape");
+}
+
 MeshPass base_pass(pg_plan p, const void* x) {
     MeshPass q;
     q.x = x;
@@ -485,6 +520,25 @@ MeshPass base_pass(pg_plan p, const void* x) {
 // ------------------------------------------------------------ mesh driver
 
 enum Want { W_OBJ = 1, W_GRAD = 2 };
+
+// A caller-owned tape of one call (pg_objective_tape / pg_adjoint_tape);
+// both null for the plan-level calls, which use the workspace's tape.
+struct CallTape {
+    void* out = nullptr;       // forward values written here
+    const void* in = nullptr;  // forward values read from here
+};
+
+// The workspace's tape may be read for x only if the last pg_objective
+// stored it from the same x and nothing has overwritten it since.
+pg_status stored_tape_ok(pg_plan p, const void* x) {
+    if (!p->tape_valid)
+        return fail(PG_ESTATE, "no stored forward values: call pg_objective first (a batched-dense "
+                               "gradient or recomputing adjoint overwrites them)");
+    if (p->tape_x != x)
+        return fail(PG_ESTATE, "the stored forward values were computed from another x "
+                               "(pg_objective was last called with a different pointer)");
+    return PG_OK;
+}
 
 TiledView tiled_view(pg_plan p) {
     TiledView v;
@@ -513,7 +567,7 @@ SmallPass small_pass(pg_plan p) {
 }
 
 pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, double* f_out,
-                   int want, hipStream_t s) {
+                   int want, const CallTape& t, hipStream_t s) {
     const MeshView& m = p->mesh;
     MeshPass q = base_pass(p, x);
     const bool f32 = p->dtype == PG_F32;
@@ -528,11 +582,14 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
         sp.f_out = obj ? f_out : nullptr;
         MeshMode mode = M_PRIMAL;
         if (!grd) {
-            q.u_store = p->at<double>(p->o_u);
+            q.u_store = t.out ? static_cast<double*>(t.out) : p->at<double>(p->o_u);
         } else {
             q.fbar = fbar;
-            if (!obj && p->opt.ckpt == PG_STORE) {
-                if (!p->tape_valid) return fail(PG_ESTATE, "no stored forward values: call pg_objective first");
+            if (!obj && t.in) {
+                q.u_in = static_cast<const double*>(t.in);
+            } else if (!obj && p->opt.ckpt == PG_STORE) {
+                pg_status ts = stored_tape_ok(p, x);
+                if (ts) return ts;
                 q.u_in = p->at<double>(p->o_u);
             }
             q.gacc = p->at<double>(p->o_small);
@@ -542,27 +599,30 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
         PG_HIP(tkern(p, true));
         PG_HIP(launch_mesh_small(m, mode, q, sp, s));
         PG_HIP(tkern(p, false));
-        if (!grd && q.u_store) {
+        if (!grd && !t.out && q.u_store) {
             p->tape_valid = true;
             p->tape_x = x;
         }
         return PG_OK;
     }
     if (!grd) {
-        q.u_store = p->at<double>(p->o_u);
+        q.u_store = t.out ? static_cast<double*>(t.out) : p->at<double>(p->o_u);
         PG_HIP(tkern(p, true));
         PG_HIP(launch_mesh_elem(m, M_PRIMAL, q, s));
         PG_HIP(tkern(p, false));
         if (f_out) PG_HIP(launch_final_sum(q.partials, p->mesh_blocks_n, f_out, s));
-        if (q.u_store) {
+        if (!t.out && q.u_store) {
             p->tape_valid = true;
             p->tape_x = x;
         }
         return PG_OK;
     }
     q.fbar = fbar;
-    if (!obj && p->opt.ckpt == PG_STORE) {
-        if (!p->tape_valid) return fail(PG_ESTATE, "no stored forward values: call pg_objective first");
+    if (!obj && t.in) {
+        q.u_in = static_cast<const double*>(t.in);
+    } else if (!obj && p->opt.ckpt == PG_STORE) {
+        pg_status ts = stored_tape_ok(p, x);
+        if (ts) return ts;
         q.u_in = p->at<double>(p->o_u);
     }
     if (p->opt.adjoint == PG_ADJ_COLOUR) {
@@ -938,7 +998,7 @@ pg_status batch_bind(pg_plan p, hipStream_t s) {
 }
 
 pg_status batch_run(pg_plan p, const void* x, const double* fbar, void* grad, double* f_out,
-                    int want, hipStream_t s) {
+                    int want, const CallTape& t, hipStream_t s) {
     const bool f32 = p->dtype == PG_F32;
     const bool acc = p->opt.accumulate != 0;
     const bool obj = (want & W_OBJ) != 0;
@@ -952,19 +1012,22 @@ pg_status batch_run(pg_plan p, const void* x, const double* fbar, void* grad, do
     q.combine = p->opt.scatter != 1;
     q.fbar = fbar;
     if (!grd) {
-        q.u_store = p->at<double>(p->o_u);
+        q.u_store = t.out ? static_cast<double*>(t.out) : p->at<double>(p->o_u);
         PG_HIP(tkern(p, true));
         PG_HIP(launch_batch(p->batch, B_PRIMAL, q, s));
         PG_HIP(tkern(p, false));
         if (f_out) PG_HIP(launch_segmented_sum(q.partials, seg, ni, f_out, s));
-        if (q.u_store) {
+        if (!t.out && q.u_store) {
             p->tape_valid = true;
             p->tape_x = x;
         }
         return PG_OK;
     }
-    if (!obj && p->opt.ckpt == PG_STORE) {
-        if (!p->tape_valid) return fail(PG_ESTATE, "no stored forward values: call pg_objective first");
+    if (!obj && t.in) {
+        q.u_in = static_cast<const double*>(t.in);
+    } else if (!obj && p->opt.ckpt == PG_STORE) {
+        pg_status ts = stored_tape_ok(p, x);
+        if (ts) return ts;
         q.u_in = p->at<double>(p->o_u);
     }
     if (f32) {
@@ -1022,15 +1085,15 @@ pg_status dense_run(pg_plan p, const void* x, const double* fbar, void* grad, do
 // --------------------------------------------------- batched dense driver
 
 pg_status bdense_run(pg_plan p, const void* X, const double* fbar, void* G, double* f_out,
-                     int want, hipStream_t s) {
+                     int want, const CallTape& t, hipStream_t s) {
     double* partials = p->at<double>(p->o_partials);
     void* V = p->ws + p->o_vmat;
     const bool grd = (want & W_GRAD) != 0;
     const bool obj = (want & W_OBJ) != 0;
     if (!grd) {
-        const bool store = p->opt.ckpt == PG_STORE;
+        const bool store = p->opt.ckpt == PG_STORE && !t.out;
         PG_HIP(tkern(p, true));
-        PG_HIP(launch_bdense_fwd(p->bd, X, partials, store ? V : nullptr, s));
+        PG_HIP(launch_bdense_fwd(p->bd, X, partials, t.out ? t.out : store ? V : nullptr, s));
         PG_HIP(tkern(p, false));
         if (f_out) PG_HIP(launch_final_sum(partials, p->bd_tiles, f_out, s));
         if (store) {
@@ -1039,25 +1102,32 @@ pg_status bdense_run(pg_plan p, const void* X, const double* fbar, void* G, doub
         }
         return PG_OK;
     }
-    if (obj || p->opt.ckpt == PG_RECOMPUTE) {
+    const void* Vin = V;
+    if (!obj && t.in) {
+        Vin = t.in;
+    } else if (obj || p->opt.ckpt == PG_RECOMPUTE) {
+        // V(X) goes to the workspace buffer, which is also the stored tape:
+        // a tape recorded from another X is gone.
         PG_HIP(launch_bdense_fwd(p->bd, X, partials, V, s));
+        p->tape_valid = false;
         if (obj && f_out) PG_HIP(launch_final_sum(partials, p->bd_tiles, f_out, s));
-    } else if (!p->tape_valid) {
-        return fail(PG_ESTATE, "no stored forward values: call pg_objective first");
+    } else {
+        pg_status ts = stored_tape_ok(p, X);
+        if (ts) return ts;
     }
     PG_HIP(tkern(p, true));
-    PG_HIP(launch_bdense_bwd(p->bd, V, fbar, G, p->opt.accumulate, s));
+    PG_HIP(launch_bdense_bwd(p->bd, Vin, fbar, G, p->opt.accumulate, s));
     PG_HIP(tkern(p, false));
     return PG_OK;
 }
 
 pg_status run_kind(pg_plan p, const void* x, const double* fbar, void* grad, double* f_out,
-                   int want, hipStream_t s) {
+                   int want, const CallTape& t, hipStream_t s) {
     switch (p->kind) {
-        case K_MESH: return mesh_run(p, x, fbar, grad, f_out, want, s);
-        case K_BATCH: return batch_run(p, x, fbar, grad, f_out, want, s);
+        case K_MESH: return mesh_run(p, x, fbar, grad, f_out, want, t, s);
+        case K_BATCH: return batch_run(p, x, fbar, grad, f_out, want, t, s);
         case K_DENSE: return dense_run(p, x, fbar, grad, f_out, want, s);
-        case K_BDENSE: return bdense_run(p, x, fbar, grad, f_out, want, s);
+        case K_BDENSE: return bdense_run(p, x, fbar, grad, f_out, want, t, s);
         case K_LAPLACE:
             return fail(PG_EUNSUPPORTED, "use pg_laplace1d_objective / pg_laplace1d_gradient");
     }
@@ -1065,10 +1135,10 @@ pg_status run_kind(pg_plan p, const void* x, const double* fbar, void* grad, dou
 }
 
 pg_status run(pg_plan p, const void* x, const double* fbar, void* grad, double* f_out, int want,
-              pg_stream stream) {
+              pg_stream stream, const CallTape& t = CallTape{}) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     PG_HIP(tmark(p, 2, true, s));
-    pg_status st = run_kind(p, x, fbar, grad, f_out, want, s);
+    pg_status st = run_kind(p, x, fbar, grad, f_out, want, t, s);
     if (st != PG_OK) return st;
     PG_HIP(tmark(p, 2, false, s));
     return PG_OK;
@@ -1089,6 +1159,8 @@ pg_options pg_default_options(void) {
     o.accumulate = 0;
     o.scatter = 0;
     o.onepass = 0;
+    o.reserved = 0;
+    o.tape_budget = 0;
     return o;
 }
 
@@ -1122,6 +1194,7 @@ pg_status pg_mesh_plan(pg_plan* plan, int64_t n_nodes, int64_t n_elems, int32_t 
     p->mesh.conn = conn;
     p->mesh.B = B;
     p->mesh.w = w;
+    if ((st = resolve_ckpt(p, sizeof(double) * (size_t)n_elems))) return drop_plan(p, st);
     layout_mesh(p);
     *workspace_bytes = p->ws_bytes;
     *plan = p;
@@ -1169,6 +1242,7 @@ pg_status pg_mesh_batch_plan(pg_plan* plan, int32_t n_inst, const pg_instance* i
     p->batch.B = B;
     p->batch.w = w;
     if (!k_in_registers(k)) p->opt.tile = 1;
+    if ((st = resolve_ckpt(p, sizeof(double) * (size_t)ne))) return drop_plan(p, st);
     layout_batch(p);
     *workspace_bytes = p->ws_bytes;
     *plan = p;
@@ -1194,6 +1268,7 @@ pg_status pg_dense_plan(pg_plan* plan, int64_t rows, int64_t cols, const void* A
     p->dense.dtype = dtype == PG_F64 ? F64 : F32;
     p->dense.A = A;
     p->dense.w = w;
+    if ((st = resolve_ckpt(p, 0))) return drop_plan(p, st);
     layout_dense(p);
     *workspace_bytes = p->ws_bytes;
     *plan = p;
@@ -1220,6 +1295,7 @@ pg_status pg_bdense_plan(pg_plan* plan, int64_t m, int64_t n, const void* A, con
     p->bd.dtype = dtype == PG_F64 ? F64 : F32;
     p->bd.A = A;
     p->bd.W = W;
+    if ((st = resolve_ckpt(p, esize(dtype) * (size_t)(m * n)))) return drop_plan(p, st);
     layout_bdense(p);
     *workspace_bytes = p->ws_bytes;
     *plan = p;
@@ -1290,7 +1366,52 @@ pg_status pg_adjoint(pg_plan p, const void* x, const double* fbar, void* grad, p
     if ((st = check_out_alias(p, grad, x_bytes(p), x, "grad"))) return st;
     if (overlap(fbar, sizeof(double) * f_count(p), grad, x_bytes(p)))
         return fail(PG_EALIAS, "fbar overlaps grad");
+    if (p->opt.ckpt == PG_STORE && (p->kind == K_MESH || p->kind == K_BATCH || p->kind == K_BDENSE) &&
+        (st = stored_tape_ok(p, x)))
+        return st;
     return run(p, x, fbar, grad, nullptr, W_GRAD, stream);
+}
+
+pg_status pg_tape_bytes(pg_plan p, size_t* bytes) {
+    g_err[0] = 0;
+    if (!p || !bytes) return fail(PG_EINVAL, "plan and bytes must not be NULL");
+    if (p->kind != K_MESH && p->kind != K_BATCH && p->kind != K_BDENSE)
+        return fail(PG_EUNSUPPORTED, "this plan kind records no tape");
+    *bytes = p->tape_bytes;
+    return PG_OK;
+}
+
+pg_status pg_objective_tape(pg_plan p, const void* x, double* f_out, void* tape, pg_stream stream) {
+    g_err[0] = 0;
+    pg_status st = need_bound(p);
+    if (st) return st;
+    if (!x && x_bytes(p) > 0) return fail(PG_EINVAL, "x is NULL");
+    if (!f_out) return fail(PG_EINVAL, "f_out is NULL");
+    if ((st = check_out_alias(p, f_out, sizeof(double) * f_count(p), x, "f_out"))) return st;
+    if ((st = check_tape(p, tape, x))) return st;
+    if (overlap(f_out, sizeof(double) * f_count(p), tape, p->tape_bytes))
+        return fail(PG_EALIAS, "f_out overlaps the tape");
+    CallTape t;
+    t.out = tape;
+    return run(p, x, nullptr, nullptr, f_out, W_OBJ, stream, t);
+}
+
+pg_status pg_adjoint_tape(pg_plan p, const double* fbar, const void* tape, void* grad,
+                          pg_stream stream) {
+    g_err[0] = 0;
+    pg_status st = need_bound(p);
+    if (st) return st;
+    if (!grad && x_bytes(p) > 0) return fail(PG_EINVAL, "grad is NULL");
+    if (!fbar) return fail(PG_EINVAL, "fbar is NULL");
+    if ((st = check_out_alias(p, grad, x_bytes(p), nullptr, "grad"))) return st;
+    if ((st = check_tape(p, tape, nullptr))) return st;
+    if (overlap(grad, x_bytes(p), tape, p->tape_bytes)) return fail(PG_EALIAS, "grad overlaps the tape");
+    if (overlap(fbar, sizeof(double) * f_count(p), grad, x_bytes(p)))
+        return fail(PG_EALIAS, "fbar overlaps grad");
+    CallTape t;
+    t.in = tape;
+    // x is not read when the forward values come from the tape.
+    return run(p, nullptr, fbar, grad, nullptr, W_GRAD, stream, t);
 }
 
 pg_status pg_hvp(pg_plan p, const void* x, const void* v, void* hv, pg_stream stream) {
@@ -1370,6 +1491,7 @@ pg_status pg_laplace1d_plan(pg_plan* plan, int64_t n, pg_dtype dtype, const pg_o
     if (!p) return fail(PG_EINVAL, "out of host memory");
     p->lap_n = n;
     p->lap_atomic = want == PG_ADJ_ATOMIC;
+    if ((st = resolve_ckpt(p, 0))) return drop_plan(p, st);
     Layout L;
     p->n_partials = (size_t)std::max<int64_t>(laplace1d_blocks(n), 1);
     p->o_partials = L.take(sizeof(double) * p->n_partials);
@@ -1479,6 +1601,92 @@ pg_status pg_jvp(pg_plan p, const void* x, const void* d, double* jvp_out, pg_st
     }
     PG_HIP(launch_mesh_elem(p->mesh, M_JVP, q, s));
     PG_HIP(launch_final_sum(q.partials, p->mesh_blocks_n, jvp_out, s));
+    return PG_OK;
+}
+
+pg_status pg_scale(pg_dtype dtype, int64_t n, const double* alpha, const void* x, void* y,
+                   pg_stream stream) {
+    g_err[0] = 0;
+    pg_status st = check_dtype(dtype);
+    if (st) return st;
+    if (n < 0) return fail(PG_EINVAL, "n must be >= 0");
+    if (!alpha) return fail(PG_EINVAL, "alpha is NULL");
+    if (n > 0 && (!x || !y)) return fail(PG_EINVAL, "x and y must not be NULL");
+    const size_t nb = esize(dtype) * (size_t)n;
+    if (x != y && overlap(x, nb, y, nb)) return fail(PG_EALIAS, "x and y overlap without being equal");
+    if (overlap(alpha, sizeof(double), y, nb)) return fail(PG_EALIAS, "alpha overlaps y");
+    PG_HIP(launch_scale(dtype == PG_F64 ? F64 : F32, n, alpha, x, y, static_cast<hipStream_t>(stream)));
+    return PG_OK;
+}
+
+pg_status pg_plan_info(pg_plan p, pg_plan_info_t* info) {
+    g_err[0] = 0;
+    if (!p || !info) return fail(PG_EINVAL, "plan and info must not be NULL");
+    pg_plan_info_t r;
+    std::memset(&r, 0, sizeof r);
+    r.kind = (int32_t)p->kind;
+    r.dtype = (int32_t)p->dtype;
+    r.adjoint = p->kind == K_LAPLACE ? (p->lap_atomic ? PG_ADJ_ATOMIC : PG_ADJ_GATHER) : p->opt.adjoint;
+    r.ckpt = p->opt.ckpt;
+    r.block = p->opt.block;
+    r.tile = p->opt.tile;
+    const bool table = (p->kind == K_MESH || p->kind == K_BATCH) && p->opt.adjoint == PG_ADJ_ATOMIC &&
+                       p->opt.scatter != 1;
+    r.lds_slots = table && p->bound ? (p->kind == K_BATCH ? 4096 : p->agg_slots) : 0;
+    r.one_launch = p->small ? 1 : 0;
+    r.n_colours = p->colour_off.empty() ? 0 : (int32_t)(p->colour_off.size() - 1);
+    r.bound = p->bound ? 1 : 0;
+    r.workspace_bytes = (int64_t)p->ws_bytes;
+    r.tape_bytes = (int64_t)p->tape_bytes;
+    r.tape_budget = p->tape_budget;
+    *info = r;
+    return PG_OK;
+}
+
+pg_status pg_plan_export(pg_plan p, int32_t what, void* host_dst, size_t capacity, size_t* bytes) {
+    g_err[0] = 0;
+    if (!p || !bytes) return fail(PG_EINVAL, "plan and bytes must not be NULL");
+    if (!p->bound) return fail(PG_ESTATE, "plan has no workspace bound (call pg_bind_workspace)");
+    if (p->kind != K_MESH) return fail(PG_EUNSUPPORTED, "only mesh plans export structures");
+    const MeshView& m = p->mesh;
+    const void* dev = nullptr;
+    const void* host = nullptr;
+    size_t nb = 0;
+    switch (what) {
+        case PG_EXPORT_CSR_OFFS:
+        case PG_EXPORT_CSR_INC:
+            if (p->opt.adjoint != PG_ADJ_GATHER)
+                return fail(PG_EUNSUPPORTED, "the transposed connectivity belongs to the gather adjoint");
+            if (what == PG_EXPORT_CSR_OFFS) {
+                dev = p->at<int32_t>(p->o_offs);
+                nb = sizeof(int32_t) * (size_t)(m.n_nodes + 1);
+            } else {
+                dev = p->at<int32_t>(p->o_inc);
+                nb = sizeof(int32_t) * (size_t)(m.n_elems * m.k);
+            }
+            break;
+        case PG_EXPORT_COLOUR_OFFS:
+        case PG_EXPORT_COLOUR_ELEMS:
+            if (p->opt.adjoint != PG_ADJ_COLOUR)
+                return fail(PG_EUNSUPPORTED, "colour classes belong to the colour adjoint");
+            if (what == PG_EXPORT_COLOUR_OFFS) {
+                host = p->colour_off.data();
+                nb = sizeof(int64_t) * p->colour_off.size();
+            } else {
+                dev = p->at<int32_t>(p->o_elist);
+                nb = sizeof(int32_t) * (size_t)m.n_elems;
+            }
+            break;
+        default: return fail(PG_EINVAL, "unknown export %d", what);
+    }
+    *bytes = nb;
+    if (!host_dst) return PG_OK;
+    if (capacity < nb) return fail(PG_EINVAL, "capacity %zu < %zu bytes", capacity, nb);
+    if (nb == 0) return PG_OK;
+    if (host)
+        std::memcpy(host_dst, host, nb);
+    else
+        PG_HIP(hipMemcpy(host_dst, dev, nb, hipMemcpyDeviceToHost));
     return PG_OK;
 }
 

@@ -5,7 +5,10 @@
 // Both products are m x m by m x n contractions, tiled 128 x 128 x 16 per
 // workgroup of 16 (FP64) or 8 (FP32) waves; each wave owns a 64 x 16 or
 // 64 x 32 block of C as MFMA 16x16x4 accumulators (FP64: v_mfma_f64_16x16x4_f64; FP32:
-// v_mfma_f32_16x16x4_f32, whose accumulation inside the instruction is FP32).
+// v_mfma_f32_16x16x4_f32, whose accumulation inside the instruction is FP32, so
+// the FP32 path adds each 16-deep k-tile's result into FP64 accumulators and
+// restarts the matrix-core accumulators from zero: FP32 sums stay 16 terms
+// long, every longer accumulation is FP64).
 // Tiles are staged k-major in LDS (double buffered, the next tile prefetched
 // into registers while the current one feeds the matrix cores).  The
 // nonlinearity and its derivative are fused into the forward epilogue, so
@@ -187,6 +190,29 @@ k_gemm_mfma(const T* __restrict__ A, const T* __restrict__ Bm, int64_t M, int64_
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < NY; ++b) acc[a][b] = MF::zero();
+    // FP32 operands: FP64 running sums of the per-k-tile MFMA results.
+    constexpr bool kWide = std::is_same<T, float>::value;
+    double wide[kWide ? 4 : 1][kWide ? NY : 1][4];
+    if constexpr (kWide) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < NY; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) wide[a][b][r] = 0.0;
+    }
+    auto fold = [&]() {
+        if constexpr (kWide) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < NY; ++b) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) wide[a][b][r] += MF::get(acc[a][b], r);
+                    acc[a][b] = MF::zero();
+                }
+        }
+    };
 
     const int li = lane & 15, lk = lane >> 4;
     auto compute = [&](int buf) {
@@ -215,12 +241,14 @@ k_gemm_mfma(const T* __restrict__ A, const T* __restrict__ Bm, int64_t M, int64_
         // even step: compute tile t from buffer 0; tile t+1 waits in s1
         if (t + 2 < nk) gload(s0, (t + 2) * BK);
         compute(0);
+        fold();
         if (t + 1 < nk) lstore(s1, 1);
         __syncthreads();
         if (t + 1 >= nk) break;
         // odd step: compute tile t+1 from buffer 1; tile t+2 waits in s0
         if (t + 3 < nk) gload(s1, (t + 3) * BK);
         compute(1);
+        fold();
         if (t + 2 < nk) lstore(s0, 0);
         __syncthreads();
     }
@@ -241,7 +269,11 @@ k_gemm_mfma(const T* __restrict__ A, const T* __restrict__ Bm, int64_t M, int64_
                 const int64_t gi = i0 + wm * 64 + x * 16 + MF::row(lk, r);
                 const int64_t gj = j0 + wn * WN + y * 16 + li;
                 if (gi < M && gj < N) {
-                    const double c = MF::get(acc[x][y], r);
+                    double c;
+                    if constexpr (kWide)
+                        c = wide[x][y][r];
+                    else
+                        c = MF::get(acc[x][y], r);
                     const int64_t o = gi * N + gj;
                     if constexpr (EPI == EPI_FWD) {
                         const double s2 = c * c, wv = to_f64(W[o]);

@@ -158,6 +158,9 @@ hipError_t launch_f64_to_f32(double* src, float* dst, int64_t n, int accumulate,
                              hipStream_t s);
 // dst (FP64) += src (FP64).
 hipError_t launch_add_f64(const double* src, double* dst, int64_t n, hipStream_t s);
+// y = alpha[0] * x (n entries of dt; FP64 product, rounded once; y may alias x).
+hipError_t launch_scale(Dtype dt, int64_t n, const double* alpha, const void* x, void* y,
+                        hipStream_t s);
 
 // Plan-time structures.
 // flag |= 1 if any conn entry is outside [0, n_nodes); cnt[node] += 1 when cnt.

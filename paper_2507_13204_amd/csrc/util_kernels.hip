@@ -78,6 +78,16 @@ k_f64_to_f32(double* __restrict__ src, float* __restrict__ dst, int64_t n, int a
     }
 }
 
+// y = alpha[0] * x in FP64, rounded once to T (y may alias x).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_scale(int64_t n, const double* __restrict__ alpha, const T* x, T* y) {
+    const double a = alpha[0];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        y[i] = static_cast<T>(a * static_cast<double>(x[i]));
+}
+
 __global__ void __launch_bounds__(256)
 k_add_f64(const double* __restrict__ src, double* __restrict__ dst, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -252,6 +262,19 @@ hipError_t launch_f64_to_f32(double* src, float* dst, int64_t n, int accumulate,
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_f64_to_f32, dim3(stream_grid(n, 256 * 4, 8192)), dim3(256), 0, s, src,
                        dst, n, accumulate, clear);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(Dtype dt, int64_t n, const double* alpha, const void* x, void* y,
+                        hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const dim3 g(stream_grid(n, 256 * 4, 8192));
+    if (dt == F64)
+        hipLaunchKernelGGL(k_scale<double>, g, dim3(256), 0, s, n, alpha,
+                           static_cast<const double*>(x), static_cast<double*>(y));
+    else
+        hipLaunchKernelGGL(k_scale<float>, g, dim3(256), 0, s, n, alpha,
+                           static_cast<const float*>(x), static_cast<float*>(y));
     return hipGetLastError();
 }
 

@@ -24,16 +24,19 @@ STATUS_NAMES = ["PG_OK", "PG_EINVAL", "PG_ERANGE", "PG_EDTYPE", "PG_EALIAS", "PG
                 "PG_EHIP", "PG_EUNSUPPORTED", "PG_ESTATE"]
 F64, F32 = 0, 1
 ADJ_AUTO, ADJ_ATOMIC, ADJ_GATHER, ADJ_COLOUR, ADJ_TILED = 0, 1, 2, 3, 4
-RECOMPUTE, STORE = 0, 1
+RECOMPUTE, STORE, CKPT_AUTO = 0, 1, 2
 WORKSPACE_ALIGN = 256
 
 ADJOINTS = {"auto": ADJ_AUTO, "atomic": ADJ_ATOMIC, "gather": ADJ_GATHER, "colour": ADJ_COLOUR,
             "tiled": ADJ_TILED}
-CKPTS = {"recompute": RECOMPUTE, "store": STORE}
+CKPTS = {"recompute": RECOMPUTE, "store": STORE, "auto": CKPT_AUTO}
+EXPORT_CSR_OFFS, EXPORT_CSR_INC, EXPORT_COLOUR_OFFS, EXPORT_COLOUR_ELEMS = 0, 1, 2, 3
 
 EXPORTS = ("pg_default_options", "pg_mesh_plan", "pg_dense_plan", "pg_bdense_plan",
            "pg_mesh_batch_plan", "pg_workspace_size", "pg_bind_workspace", "pg_objective",
            "pg_gradient", "pg_adjoint", "pg_hvp", "pg_jvp", "pg_timing", "pg_timing_read",
+           "pg_tape_bytes", "pg_objective_tape", "pg_adjoint_tape", "pg_scale", "pg_plan_info",
+           "pg_plan_export",
            "pg_laplace1d_plan", "pg_laplace1d_objective", "pg_laplace1d_gradient",
            "pg_plan_destroy", "pg_last_error", "pg_version",
            "pg_prog_create", "pg_prog_input", "pg_prog_const", "pg_prog_scale", "pg_prog_stencil",
@@ -62,7 +65,17 @@ class ProgStats(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("adjoint", ctypes.c_int32), ("ckpt", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("accumulate", ctypes.c_int32),
-                ("scatter", ctypes.c_int32), ("onepass", ctypes.c_int32)]
+                ("scatter", ctypes.c_int32), ("onepass", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tape_budget", ctypes.c_int64)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("adjoint", ctypes.c_int32),
+                ("ckpt", ctypes.c_int32), ("block", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("lds_slots", ctypes.c_int32), ("one_launch", ctypes.c_int32),
+                ("n_colours", ctypes.c_int32), ("bound", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_int64), ("tape_bytes", ctypes.c_int64),
+                ("tape_budget", ctypes.c_int64)]
 
 
 class Instance(ctypes.Structure):
@@ -102,6 +115,12 @@ def lib():
     L.pg_adjoint.argtypes = [_VP, _VP, _VP, _VP, _VP]
     L.pg_hvp.argtypes = [_VP, _VP, _VP, _VP, _VP]
     L.pg_jvp.argtypes = [_VP, _VP, _VP, _VP, _VP]
+    L.pg_tape_bytes.argtypes = [_VP, _SZP]
+    L.pg_objective_tape.argtypes = [_VP, _VP, _VP, _VP, _VP]
+    L.pg_adjoint_tape.argtypes = [_VP, _VP, _VP, _VP, _VP]
+    L.pg_scale.argtypes = [ctypes.c_int, _I64, _VP, _VP, _VP, _VP]
+    L.pg_plan_info.argtypes = [_VP, ctypes.POINTER(PlanInfo)]
+    L.pg_plan_export.argtypes = [_VP, _I32, _VP, ctypes.c_size_t, _SZP]
     L.pg_plan_destroy.argtypes = [_VP]
     L.pg_timing.argtypes = [_VP, _I32]
     L.pg_timing_read.argtypes = [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]
@@ -139,6 +158,8 @@ def lib():
     for name in ("pg_mesh_plan", "pg_dense_plan", "pg_bdense_plan", "pg_mesh_batch_plan",
                  "pg_workspace_size", "pg_bind_workspace", "pg_objective", "pg_gradient",
                  "pg_adjoint", "pg_hvp", "pg_jvp", "pg_timing", "pg_timing_read", "pg_plan_destroy",
+                 "pg_tape_bytes", "pg_objective_tape", "pg_adjoint_tape", "pg_scale",
+                 "pg_plan_info", "pg_plan_export",
                  "pg_laplace1d_plan", "pg_laplace1d_objective", "pg_laplace1d_gradient"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -151,7 +172,8 @@ def check(code: int, where: str):
 
 
 def make_options(adjoint="auto", ckpt="recompute", block: int = 0, tile: int = 0,
-                 accumulate: bool = False, scatter: int = 0, onepass: bool = True) -> Options:
+                 accumulate: bool = False, scatter: int = 0, onepass: bool = True,
+                 tape_budget: int = 0) -> Options:
     o = Options()
     o.adjoint = ADJOINTS[adjoint] if isinstance(adjoint, str) else int(adjoint)
     o.ckpt = CKPTS[ckpt] if isinstance(ckpt, str) else int(ckpt)
@@ -160,6 +182,8 @@ def make_options(adjoint="auto", ckpt="recompute", block: int = 0, tile: int = 0
     o.accumulate = int(bool(accumulate))
     o.scatter = int(scatter)
     o.onepass = 0 if onepass else 1
+    o.reserved = 0
+    o.tape_budget = int(tape_budget)
     return o
 
 
@@ -217,6 +241,64 @@ class _Plan:
         except Exception:
             pass
 
+    def info(self) -> dict:
+        """pg_plan_info: the plan's resolved choices (ckpt, adjoint, LDS table, ...)."""
+        st = PlanInfo()
+        check(lib().pg_plan_info(self._plan, ctypes.byref(st)), "pg_plan_info")
+        return {name: getattr(st, name) for name, _ in PlanInfo._fields_}
+
+    def tape_bytes(self) -> int:
+        sz = ctypes.c_size_t()
+        check(lib().pg_tape_bytes(self._plan, ctypes.byref(sz)), "pg_tape_bytes")
+        return sz.value
+
+    def new_tape(self, device) -> torch.Tensor:
+        """A caller-owned tape for one forward pass (pg_objective_tape)."""
+        n = self.tape_bytes()
+        return torch.empty((n + 15) // 16 * 2, dtype=torch.float64, device=device)
+
+    def objective_tape(self, x, tape, f_shape=(), stream=None, f_out=None):
+        _need_cuda(x, tape)
+        f = torch.empty(f_shape, dtype=torch.float64, device=x.device) if f_out is None else f_out
+        check(lib().pg_objective_tape(self._plan, _ptr(x), _ptr(f), _ptr(tape), _stream(stream)),
+              "pg_objective_tape")
+        return f
+
+    def adjoint_tape(self, fbar, tape, like, out=None, stream=None):
+        _need_cuda(fbar, tape, out)
+        g = torch.empty_like(like) if out is None else out
+        check(lib().pg_adjoint_tape(self._plan, _ptr(fbar), _ptr(tape), _ptr(g), _stream(stream)),
+              "pg_adjoint_tape")
+        return g
+
+    # What the forward of an autograd Function keeps for its backward:
+    #   "gradient":  f and the gradient in one pg_gradient call; the backward
+    #                scales the saved gradient by grad_output (pg_scale);
+    #   "store":     the forward values on a per-call tape (pg_objective_tape);
+    #   "recompute": nothing; the backward recomputes them (pg_adjoint).
+    # "auto" takes the first of these whose saved bytes fit the budget
+    # (autograd_budget bytes, or a quarter of the free device memory when the
+    # objective is made).
+    _POLICIES = ("gradient", "store", "recompute")
+
+    def _resolve_autograd(self, policy, budget, x_bytes, device, allowed):
+        if policy != "auto":
+            if policy not in allowed:
+                raise PgError(EINVAL, "autograd", f"policy {policy!r} not offered here ({allowed})")
+            return policy
+        if not budget:
+            free, _ = torch.cuda.mem_get_info(device)
+            budget = free // 4
+        self.autograd_budget = int(budget)
+        saved = {"gradient": x_bytes,
+                 "store": self.tape_bytes() if "store" in allowed else None}
+        for pol in self._POLICIES:
+            if pol not in allowed:
+                continue
+            if pol == "recompute" or saved[pol] <= budget:
+                return pol
+        return "recompute"
+
     def timing(self, mode: int):
         """0 off, 1 time the dominant kernel of each call, 2 time each call."""
         check(lib().pg_timing(self._plan, int(mode)), "pg_timing")
@@ -255,7 +337,8 @@ class MeshObjective(_Plan):
 
     def __init__(self, conn: torch.Tensor, B: torch.Tensor, w: torch.Tensor, n_nodes: int,
                  adjoint="auto", ckpt="recompute", block: int = 0, tile: int = 0,
-                 accumulate: bool = False, scatter: int = 0, onepass: bool = True, stream=None):
+                 accumulate: bool = False, scatter: int = 0, onepass: bool = True, stream=None,
+                 tape_budget: int = 0, autograd: str = "auto", autograd_budget: int = 0):
         super().__init__()
         _need_cuda(conn, B, w)
         if conn.dtype != torch.int32:
@@ -265,13 +348,31 @@ class MeshObjective(_Plan):
         self.conn, self.B, self.w = conn, B, w
         self.n_nodes, self.n_elems, self.k = int(n_nodes), int(E), int(k)
         self.dtype = B.dtype
-        self.options = make_options(adjoint, ckpt, block, tile, accumulate, scatter, onepass)
+        self.options = make_options(adjoint, ckpt, block, tile, accumulate, scatter, onepass,
+                                    tape_budget)
         sz = ctypes.c_size_t()
         check(lib().pg_mesh_plan(ctypes.byref(self._plan), self.n_nodes, E, k, _ptr(conn),
                                  _ptr(B), _ptr(w), _dtype_code(B), ctypes.byref(self.options),
                                  ctypes.byref(sz)), "pg_mesh_plan")
         self.workspace_bytes = sz.value
         self._bind(conn.device, stream)
+        self.autograd_budget = int(autograd_budget)
+        self.autograd_policy = self._resolve_autograd(
+            autograd, autograd_budget, self.n_nodes * B.element_size(), conn.device,
+            ("gradient", "store", "recompute"))
+
+    def export(self, what: int) -> "np.ndarray":
+        """pg_plan_export: a bound plan's transposed connectivity or colour
+        classes, copied to the host."""
+        import numpy as np
+        sz = ctypes.c_size_t()
+        check(lib().pg_plan_export(self._plan, int(what), None, 0, ctypes.byref(sz)),
+              "pg_plan_export")
+        dt = np.int64 if what == EXPORT_COLOUR_OFFS else np.int32
+        out = np.empty(sz.value // np.dtype(dt).itemsize, dtype=dt)
+        check(lib().pg_plan_export(self._plan, int(what), out.ctypes.data_as(ctypes.c_void_p),
+                                   out.nbytes, ctypes.byref(sz)), "pg_plan_export")
+        return out
 
     def objective(self, x, stream=None, f_out=None):
         _need_cuda(x)
@@ -302,7 +403,8 @@ class MeshObjective(_Plan):
 class DenseObjective(_Plan):
     """f(x) = sum_i w_i psi((A x)_i) and its gradient."""
 
-    def __init__(self, A: torch.Tensor, w: torch.Tensor, accumulate: bool = False, stream=None):
+    def __init__(self, A: torch.Tensor, w: torch.Tensor, accumulate: bool = False, stream=None,
+                 autograd: str = "auto", autograd_budget: int = 0):
         super().__init__()
         _need_cuda(A, w)
         self.A, self.w = A, w
@@ -314,6 +416,10 @@ class DenseObjective(_Plan):
               "pg_dense_plan")
         self.workspace_bytes = sz.value
         self._bind(A.device, stream)
+        self.autograd_budget = int(autograd_budget)
+        self.autograd_policy = self._resolve_autograd(
+            autograd, autograd_budget, self.cols * A.element_size(), A.device,
+            ("gradient", "recompute"))
 
     def objective(self, x, stream=None, f_out=None):
         _need_cuda(x)
@@ -331,19 +437,24 @@ class DenseObjective(_Plan):
 class BatchedDense(_Plan):
     """f(X) = sum W (.) psi(A X) with both products on the matrix cores."""
 
-    def __init__(self, A: torch.Tensor, W: torch.Tensor, ckpt="store", accumulate: bool = False,
-                 stream=None):
+    def __init__(self, A: torch.Tensor, W: torch.Tensor, ckpt="auto", accumulate: bool = False,
+                 stream=None, tape_budget: int = 0, autograd: str = "auto",
+                 autograd_budget: int = 0):
         super().__init__()
         _need_cuda(A, W)
         self.A, self.W = A, W
         self.m, self.n = int(W.shape[0]), int(W.shape[1])
-        self.options = make_options(ckpt=ckpt, accumulate=accumulate)
+        self.options = make_options(ckpt=ckpt, accumulate=accumulate, tape_budget=tape_budget)
         sz = ctypes.c_size_t()
         check(lib().pg_bdense_plan(ctypes.byref(self._plan), self.m, self.n, _ptr(A), _ptr(W),
                                    _dtype_code(A), ctypes.byref(self.options), ctypes.byref(sz)),
               "pg_bdense_plan")
         self.workspace_bytes = sz.value
         self._bind(A.device, stream)
+        self.autograd_budget = int(autograd_budget)
+        self.autograd_policy = self._resolve_autograd(
+            autograd, autograd_budget, self.m * self.n * W.element_size(), A.device,
+            ("gradient", "store", "recompute"))
 
     def objective(self, X, stream=None, f_out=None):
         _need_cuda(X)
@@ -364,7 +475,8 @@ class MeshBatch(_Plan):
 
     def __init__(self, inst, conn: torch.Tensor, B: torch.Tensor, w: torch.Tensor,
                  ckpt="recompute", block: int = 0, tile: int = 0, accumulate: bool = False,
-                 scatter: int = 0, stream=None):
+                 scatter: int = 0, stream=None, tape_budget: int = 0, autograd: str = "auto",
+                 autograd_budget: int = 0):
         super().__init__()
         _need_cuda(conn, B, w)
         self.conn, self.B, self.w = conn, B, w
@@ -375,13 +487,18 @@ class MeshBatch(_Plan):
             arr[i] = Instance(nn, ne, no, eo)
         self.n_nodes = max([r[0] + r[2] for r in rows], default=0)
         k = conn.shape[1] if conn.dim() == 2 else 8
-        self.options = make_options("atomic", ckpt, block, tile, accumulate, scatter)
+        self.options = make_options("atomic", ckpt, block, tile, accumulate, scatter,
+                                    tape_budget=tape_budget)
         sz = ctypes.c_size_t()
         check(lib().pg_mesh_batch_plan(ctypes.byref(self._plan), self.n_inst, arr, k, _ptr(conn),
                                        _ptr(B), _ptr(w), _dtype_code(B), ctypes.byref(self.options),
                                        ctypes.byref(sz)), "pg_mesh_batch_plan")
         self.workspace_bytes = sz.value
         self._bind(conn.device, stream)
+        # per-instance seeds: the saved-gradient policy does not apply
+        self.autograd_budget = int(autograd_budget)
+        self.autograd_policy = self._resolve_autograd(
+            autograd, autograd_budget, 0, conn.device, ("store", "recompute"))
 
     def objective(self, x, stream=None, f_out=None):
         _need_cuda(x)
@@ -638,39 +755,87 @@ class Program:
 
 # ------------------------------------------------------------------ autograd
 
-class MeshFn(torch.autograd.Function):
-    """y = f(x) for a MeshObjective; backward seeds pg_adjoint with grad_output.
+def scale(alpha: torch.Tensor, x: torch.Tensor, out: Optional[torch.Tensor] = None,
+          stream=None) -> torch.Tensor:
+    """out = alpha[0] * x on the device (pg_scale; alpha one float64)."""
+    _need_cuda(alpha, x, out)
+    y = torch.empty_like(x) if out is None else out
+    check(lib().pg_scale(_dtype_code(x), x.numel(), _ptr(alpha), _ptr(x), _ptr(y),
+                         _stream(stream)), "pg_scale")
+    return y
 
-    With ckpt='store' the forward keeps u_e in the plan's workspace and the
-    backward reads it; with 'recompute' the backward gathers x again."""
+
+def _seed(gout) -> torch.Tensor:
+    return gout.detach().to(torch.float64).contiguous().reshape(-1)
+
+
+class _ObjectiveFn(torch.autograd.Function):
+    """Shared forward/backward of the scalar-objective Functions.  The
+    forward follows the objective's autograd_policy when a gradient will be
+    needed (grad mode on and x requiring grad), and evaluates f alone
+    otherwise."""
+
+    @classmethod
+    def apply(cls, x, obj):
+        return super().apply(x, obj, bool(torch.is_grad_enabled() and x.requires_grad))
 
     @staticmethod
-    def forward(ctx, x, obj: MeshObjective):
-        f = obj.objective(x.detach().contiguous())
+    def forward(ctx, x, obj, want_grad):
+        xd = x.detach().contiguous()
         ctx.obj = obj
-        ctx.save_for_backward(x)
+        ctx.policy = obj.autograd_policy if want_grad else "none"
+        if ctx.policy == "gradient":
+            f, g = obj.gradient(xd)
+            ctx.save_for_backward(g)
+        elif ctx.policy == "store":
+            tape = obj.new_tape(xd.device)
+            f = obj.objective_tape(xd, tape, f_shape=_ObjectiveFn._fshape(obj))
+            ctx.save_for_backward(tape, xd)
+        else:
+            f = obj.objective(xd)
+            ctx.save_for_backward(xd)
         return f
 
     @staticmethod
-    def backward(ctx, gout):
-        (x,) = ctx.saved_tensors
-        fbar = gout.detach().to(torch.float64).contiguous().reshape(1)
-        g = ctx.obj.adjoint(x.detach().contiguous(), fbar)
-        return g, None
-
-
-class DenseFn(torch.autograd.Function):
-    @staticmethod
-    def forward(ctx, x, obj: DenseObjective):
-        ctx.obj = obj
-        ctx.save_for_backward(x)
-        return obj.objective(x.detach().contiguous())
+    def _fshape(obj):
+        return (obj.n_inst,) if isinstance(obj, MeshBatch) else ()
 
     @staticmethod
     def backward(ctx, gout):
-        (x,) = ctx.saved_tensors
-        fbar = gout.detach().to(torch.float64).contiguous().reshape(1)
-        return ctx.obj.adjoint(x.detach().contiguous(), fbar), None
+        fbar = _seed(gout)
+        if ctx.policy == "gradient":
+            (g,) = ctx.saved_tensors
+            return scale(fbar, g), None, None
+        if ctx.policy == "store":
+            tape, xd = ctx.saved_tensors
+            return ctx.obj.adjoint_tape(fbar, tape, xd), None, None
+        if ctx.policy == "none":
+            raise PgError(ESTATE, "backward", "the forward ran without a gradient requested")
+        (xd,) = ctx.saved_tensors
+        return ctx.obj.adjoint(xd, fbar), None, None
+
+
+class MeshFn(_ObjectiveFn):
+    """y = f(x) for a MeshObjective.  What the forward keeps for the backward
+    is the objective's autograd_policy: the gradient itself (f and the
+    gradient in one pass; the backward multiplies by grad_output), u_e on a
+    tape owned by this call, or nothing (the backward gathers x again)."""
+
+
+class DenseFn(_ObjectiveFn):
+    """y = f(x) for a DenseObjective (policies "gradient" or "recompute")."""
+
+
+class BatchedDenseFn(_ObjectiveFn):
+    """f(X) = sum W (.) psi(A X): forward product with the psi epilogue;
+    the policy keeps the gradient, V = W (.) psi'(A X) on a per-call tape, or
+    nothing (the backward recomputes V)."""
+
+
+class MeshBatchFn(_ObjectiveFn):
+    """Per-instance objectives of a MeshBatch (a vector output): the policy
+    keeps u_e on a per-call tape or nothing; the backward seeds each
+    instance with its own grad_output entry."""
 
 
 class ProgramFn(torch.autograd.Function):
@@ -697,32 +862,3 @@ class ProgramFn(torch.autograd.Function):
         return (None, *gs)
 
 
-class BatchedDenseFn(torch.autograd.Function):
-    """f(X) = sum W (.) psi(A X); forward GEMM with the psi epilogue (stores
-    V = W (.) psi'(A X) when ckpt='store'), backward GEMM A^T V."""
-
-    @staticmethod
-    def forward(ctx, X, obj: BatchedDense):
-        ctx.obj = obj
-        ctx.save_for_backward(X)
-        return obj.objective(X.detach().contiguous())
-
-    @staticmethod
-    def backward(ctx, gout):
-        (X,) = ctx.saved_tensors
-        fbar = gout.detach().to(torch.float64).contiguous().reshape(1)
-        return ctx.obj.adjoint(X.detach().contiguous(), fbar), None
-
-
-class MeshBatchFn(torch.autograd.Function):
-    @staticmethod
-    def forward(ctx, x, obj: MeshBatch):
-        ctx.obj = obj
-        ctx.save_for_backward(x)
-        return obj.objective(x.detach().contiguous())
-
-    @staticmethod
-    def backward(ctx, gout):
-        (x,) = ctx.saved_tensors
-        fbar = gout.detach().to(torch.float64).contiguous()
-        return ctx.obj.adjoint(x.detach().contiguous(), fbar), None

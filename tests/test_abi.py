@@ -29,12 +29,91 @@ def test_library_exports_every_declared_symbol():
     L = P.lib()
     for name in declared_functions():
         assert hasattr(L, name), name
-    assert L.pg_version() == 1
+    assert L.pg_version() == 2
 
 
 def test_default_options():
     o = P.lib().pg_default_options()
     assert (o.adjoint, o.ckpt, o.block, o.tile, o.accumulate, o.scatter) == (0, 0, 0, 0, 0, 0)
+    assert (o.onepass, o.reserved, o.tape_budget) == (0, 0, 0)
+    assert ctypes.sizeof(P.Options) == 40  # 8 int32 (one reserved) + one int64
+
+
+def _info(plan):
+    st = P.PlanInfo()
+    assert P.lib().pg_plan_info(plan, ctypes.byref(st)) == P.OK
+    return st
+
+
+@pytest.mark.parametrize("budget,expect", [(900 * 8, P.STORE), (900 * 8 - 1, P.RECOMPUTE),
+                                           (1 << 40, P.STORE)])
+def test_ckpt_auto_is_chosen_by_the_tape_budget(budget, expect):
+    """PG_CKPT_AUTO stores the tape (u_e, 8 bytes per element) when it fits the
+    caller's budget and recomputes otherwise; the choice is visible in
+    pg_plan_info and in the workspace size (the stored tape lives there)."""
+    opts = P.make_options(ckpt="auto", onepass=False, tape_budget=budget)
+    st, plan, ws = plan_mesh(n_nodes=1000, n_elems=900, k=8, opts=opts)
+    assert st == P.OK
+    info = _info(plan)
+    assert info.ckpt == expect and info.tape_bytes == 900 * 8 and info.tape_budget == budget
+    assert info.bound == 0 and info.lds_slots == 0 and info.kind == 1
+    _, ref, ws_ref = plan_mesh(n_nodes=1000, n_elems=900, k=8,
+                               opts=P.make_options(ckpt=["recompute", "store"][expect],
+                                                   onepass=False))
+    assert ws == ws_ref
+    sz = ctypes.c_size_t()
+    assert P.lib().pg_tape_bytes(plan, ctypes.byref(sz)) == P.OK and sz.value == 900 * 8
+    P.lib().pg_plan_destroy(plan)
+    P.lib().pg_plan_destroy(ref)
+
+
+def test_bdense_tape_is_v_and_dense_has_none():
+    L = P.lib()
+    plan = ctypes.c_void_p()
+    sz = ctypes.c_size_t()
+    o = P.make_options(ckpt="auto", tape_budget=64 * 32 * 4)
+    assert L.pg_bdense_plan(ctypes.byref(plan), 64, 32, FAKE, FAKE, P.F32, ctypes.byref(o),
+                            ctypes.byref(sz)) == P.OK
+    assert _info(plan).ckpt == P.STORE
+    t = ctypes.c_size_t()
+    assert L.pg_tape_bytes(plan, ctypes.byref(t)) == P.OK and t.value == 64 * 32 * 4
+    L.pg_plan_destroy(plan)
+    assert L.pg_dense_plan(ctypes.byref(plan), 100, 50, FAKE, FAKE, P.F64, ctypes.byref(o),
+                           ctypes.byref(sz)) == P.OK
+    assert _info(plan).ckpt == P.RECOMPUTE  # nothing to store
+    assert L.pg_tape_bytes(plan, ctypes.byref(t)) == P.EUNSUPPORTED
+    L.pg_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("field,value", [("reserved", 1), ("tape_budget", -1), ("ckpt", 3)])
+def test_bad_checkpoint_options(field, value):
+    o = P.make_options()
+    setattr(o, field, value)
+    st, plan, _ = plan_mesh(opts=o)
+    assert st == P.EINVAL and not plan.value
+
+
+def test_tape_calls_and_exports_need_a_bound_plan():
+    st, plan, _ = plan_mesh(opts=P.make_options(ckpt="store"))
+    L = P.lib()
+    assert L.pg_objective_tape(plan, FAKE, FAKE, FAKE, None) == P.ESTATE
+    assert L.pg_adjoint_tape(plan, FAKE, FAKE, FAKE, None) == P.ESTATE
+    sz = ctypes.c_size_t()
+    assert L.pg_plan_export(plan, P.EXPORT_CSR_OFFS, None, 0, ctypes.byref(sz)) == P.ESTATE
+    L.pg_plan_destroy(plan)
+
+
+def test_scale_argument_checks():
+    L = P.lib()
+    assert L.pg_scale(7, 10, FAKE, FAKE, FAKE, None) == P.EDTYPE
+    assert L.pg_scale(P.F64, -1, FAKE, FAKE, FAKE, None) == P.EINVAL
+    assert L.pg_scale(P.F64, 10, None, FAKE, FAKE + 4096, None) == P.EINVAL
+    assert L.pg_scale(P.F64, 10, FAKE + 8192, FAKE, None, None) == P.EINVAL
+    # y overlapping x without being x
+    assert L.pg_scale(P.F64, 10, FAKE + 8192, FAKE, FAKE + 8, None) == P.EALIAS
+    assert L.pg_scale(P.F32, 10, FAKE + 4096 + 16, FAKE, FAKE + 4096, None) == P.EALIAS
+    # n = 0 enqueues nothing
+    assert L.pg_scale(P.F64, 0, FAKE, None, None, None) == P.OK
 
 
 FAKE = 1 << 20  # an aligned non-null address; plan creation never dereferences it

@@ -10,12 +10,13 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.mark.parametrize("ckpt", ["store", "recompute"])
+@pytest.mark.parametrize("policy", ["gradient", "store", "recompute"])
 @pytest.mark.parametrize("adj", ["atomic", "gather"])
-def test_meshfn_backward_matches_oracle_and_fd(ckpt, adj):
+def test_meshfn_backward_matches_oracle_and_fd(policy, adj):
     from paper_2507_13204_amd import MeshFn, MeshObjective
     m = inputs.hex_mesh(12, seed=70)
-    obj = MeshObjective(to_dev(m.conn), to_dev(m.B), to_dev(m.w), m.n_nodes, adjoint=adj, ckpt=ckpt)
+    obj = MeshObjective(to_dev(m.conn), to_dev(m.B), to_dev(m.w), m.n_nodes, adjoint=adj,
+                        autograd=policy)
     x = to_dev(m.x).requires_grad_(True)
     f = MeshFn.apply(x, obj)
     (3.0 * f).backward()

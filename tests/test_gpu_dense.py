@@ -1,4 +1,6 @@
 """Parity of the dense (team/vector) and batched dense (MFMA) paths."""
+import math
+
 import numpy as np
 import pytest
 
@@ -85,18 +87,76 @@ def test_bdense_parity_f32(m, n):
     assert srel(f.item(), f_ref) <= TOL_F32 and rel(G.cpu().numpy(), G_ref) <= TOL_F32
 
 
-def test_bdense_full_size_sampled_columns():
-    """A 4096 x 4096, X 4096 x 1024: sampled columns against the Dot2 oracle."""
-    b = inputs.batched_dense(4096, 1024)
+# 16 columns of the 4096 x 1024 benchmark: both ends, every tile column
+# boundary pair of one 128-wide tile, and spread samples.
+FULL_COLS = [0, 1, 63, 64, 127, 128, 129, 255, 256, 511, 512, 700, 895, 1000, 1022, 1023]
+
+
+@pytest.fixture(scope="module")
+def bd_full():
+    return inputs.batched_dense(4096, 1024)
+
+
+def test_bdense_full_size_sampled_columns(bd_full):
+    """A 4096 x 4096, X 4096 x 1024, FP64 MFMA: 16 gradient columns against the
+    Dot2 oracle, f against the fast oracle."""
+    b = bd_full
     obj, X = _bdense(b)
     f, G = obj.gradient(X)
-    cols = [0, 1, 511, 1000, 1023]
-    fc, Gc = oracle.bdense_columns(b.A, b.X, b.W, cols)
+    fc, Gc = oracle.bdense_columns(b.A, b.X, b.W, FULL_COLS)
     Gh = G.cpu().numpy()
-    for t, c in enumerate(cols):
-        assert rel(Gh[:, c], Gc[:, t]) <= TOL_F64_G
+    for t, c in enumerate(FULL_COLS):
+        assert rel(Gh[:, c], Gc[:, t]) <= TOL_F64_G, c
     f_ref, _ = oracle.bdense_gradient_fast(b.A, b.X, b.W)
     assert srel(f.item(), f_ref) <= TOL_F64_F
+
+
+def test_bdense_full_size_f32(bd_full):
+    """FP32 storage on the FP32 matrix cores at the benchmark shape: f and 16
+    gradient columns against the Dot2 oracle on the FP32-rounded inputs
+    (1e-5); the error against the FP64-input oracle is reported."""
+    b = bd_full
+    obj, X = _bdense(b, torch.float32)
+    f, G = obj.gradient(X)
+    A32, X32, W32 = (a.astype(np.float32).astype(np.float64) for a in (b.A, b.X, b.W))
+    fc, Gc = oracle.bdense_columns(A32, X32, W32, FULL_COLS)
+    Gh = G.cpu().numpy().astype(np.float64)
+    errs = [rel(Gh[:, c], Gc[:, t]) for t, c in enumerate(FULL_COLS)]
+    assert max(errs) <= TOL_F32, max(errs)
+    f_ref, _ = oracle.bdense_gradient_fast(A32, X32, W32)
+    assert srel(f.item(), f_ref) <= TOL_F32
+    f64_ref, _ = oracle.bdense_gradient_fast(b.A, b.X, b.W)
+    _, Gc64 = oracle.bdense_columns(b.A, b.X, b.W, FULL_COLS)
+    e64 = max(rel(Gh[:, c], Gc64[:, t]) for t, c in enumerate(FULL_COLS))
+    print(f"bdense FP32 4096x4096x1024: gradient columns {max(errs):.2e} (rounded inputs), "
+          f"{e64:.2e} (FP64 inputs); f {srel(f.item(), f_ref):.2e} / {srel(f.item(), f64_ref):.2e}")
+    assert e64 <= 1e-4
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_bdense_fn_full_size_fd_16_directions(bd_full, dtype):
+    """The autograd form at 4096 x 1024: central differences of the GPU
+    objective on 16 random directions against <G, D>.  FP64: h = 1e-4,
+    1e-6 relative.  FP32: the perturbed points are rounded to FP32, so the
+    difference is taken against the exact step Xp - Xm; h = 1e-2 keeps the
+    FP32 rounding of f(Xp) - f(Xm) near 1e-6 and the third-order term near
+    1e-6 relative; bar 1e-4."""
+    from paper_2507_13204_amd import BatchedDense, BatchedDenseFn
+    b = bd_full
+    obj = BatchedDense(to_dev(b.A, dtype), to_dev(b.W, dtype))
+    X = to_dev(b.X, dtype).requires_grad_(True)
+    BatchedDenseFn.apply(X, obj).backward()
+    G = X.grad.double()
+    h, tol = (1e-4, 1e-6) if dtype == torch.float64 else (1e-2, 1e-4)
+    with torch.no_grad():
+        for D in inputs.fd_directions(b.X.shape, 16, seed=33):
+            Dt = to_dev(D)
+            Xp = (X.detach().double() + h * Dt).to(dtype)
+            Xm = (X.detach().double() - h * Dt).to(dtype)
+            fp = obj.objective(Xp).item()
+            fm = obj.objective(Xm).item()
+            slope = (G * (Xp.double() - Xm.double())).sum().item()
+            assert abs((fp - fm) - slope) <= tol * max(1.0, abs(slope)), (fp - fm, slope)
 
 
 def test_bdense_misaligned_operand_takes_the_scalar_path():

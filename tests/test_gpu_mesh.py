@@ -45,6 +45,8 @@ MESHES = {
     "rand_k4": lambda: inputs.random_mesh(500, 1333, 4, 8),
     "rand_k5": lambda: inputs.random_mesh(700, 999, 5, 9),    # runtime-k kernel
     "rand_k3": lambda: inputs.random_mesh(50, 77, 3, 10),
+    "rand_k1": lambda: inputs.random_mesh(50, 400, 1, 23),        # one node per element
+    "rand_k32": lambda: inputs.random_mesh(20000, 300, 32, 24),   # PG_MAX_K nodes per element
 }
 
 
@@ -243,6 +245,56 @@ def test_hex128_full_size_parity():
     obj, x = _obj(m, "f32")
     f, g = obj.gradient(x)
     _check(m, f.item(), g.cpu().numpy(), "f32")
+
+
+@pytest.mark.parametrize("adj", ["gather", "colour", "tiled"])
+def test_hex128_deterministic_variants_are_bitwise_repeatable(adj):
+    """At the benchmark size (the tiled adjoint's staging area is largest
+    here): three gradients, bitwise equal, and equal to the oracle."""
+    m = inputs.hex_mesh(128)
+    obj, x = _obj(m, "f64", adjoint=adj)
+    outs = [obj.gradient(x) for _ in range(3)]
+    _check(m, outs[0][0].item(), outs[0][1].cpu().numpy())
+    for f, g in outs[1:]:
+        assert f.item() == outs[0][0].item()
+        assert torch.equal(g, outs[0][1])
+
+
+@pytest.mark.parametrize("adj,onepass", [("atomic", True), ("atomic", False), ("gather", True),
+                                         ("colour", True), ("tiled", True)])
+@pytest.mark.parametrize("bad", ["nan", "inf", "huge"])
+def test_non_finite_values_propagate_to_the_touched_nodes_only(adj, onepass, bad):
+    """NaN or Inf in x (or an x whose square overflows) reaches exactly the
+    gradient entries of the nodes that share an element with it, as in the
+    oracle; every other entry is unaffected, and nothing traps.  f is not
+    finite on either side (the oracle's compensated sum turns an infinite
+    sum into NaN, the plain sum keeps Inf)."""
+    m = inputs.hex_mesh(23, seed=6)
+    xh = m.x.copy()
+    node = 11 + 23 * (7 + 23 * 5)
+    xh[node] = {"nan": np.nan, "inf": np.inf, "huge": 1e200}[bad]
+    mm = inputs.Mesh(m.n_nodes, m.n_elems, m.k, m.conn, m.B, m.w, xh, m.name)
+    obj, x = _obj(mm, "f64", adjoint=adj, onepass=onepass)
+    f, g = obj.gradient(x)
+    with np.errstate(all="ignore"):
+        f_ref, g_ref = _oracle_grad(mm)
+    gh = g.cpu().numpy()
+    assert not np.isfinite(f.item()) and not np.isfinite(f_ref)
+    assert np.array_equal(np.isnan(gh), np.isnan(g_ref))
+    assert np.array_equal(np.isinf(gh), np.isinf(g_ref))
+    touched = np.unique(m.conn[np.any(m.conn == node, axis=1)])
+    other = np.setdiff1d(np.arange(m.n_nodes), touched)
+    if bad == "huge":
+        # psi'(s) = s + s/(1 + s^2) stays finite: the touched entries are
+        # about 1e200 (compared after scaling, so the norms do not overflow)
+        assert rel(gh[touched] * 1e-190, g_ref[touched] * 1e-190) <= TOL_F64_G
+    else:
+        assert np.array_equal(np.flatnonzero(~np.isfinite(g_ref)), touched)
+    assert np.all(np.isfinite(g_ref[other]))
+    assert rel(gh[other], g_ref[other]) <= TOL_F64_G
+    # the next call on clean input is unaffected (one-launch buffers are clear)
+    f2, g2 = obj.gradient(to_dev(m.x))
+    _check(m, f2.item(), g2.cpu().numpy())
 
 
 @pytest.mark.parametrize("name", ["hex23", "rand_k8", "rand_k4", "chain10k"])

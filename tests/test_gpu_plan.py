@@ -1,0 +1,75 @@
+"""The integer structures a bound plan builds (transposed connectivity on the
+GPU, colour classes on the host), compared bit for bit with the oracle's
+independent constructions."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_13204_amd import inputs
+from _helpers import to_dev
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+MESHES = {
+    "hex17": lambda: inputs.hex_mesh(17, seed=5),
+    "hex128": lambda: inputs.hex_mesh(128),
+    "rand_k5_repeats": lambda: inputs.random_mesh(300, 2000, 5, 21),
+    "rand_k8_repeats": lambda: inputs.random_mesh(900, 2500, 8, 22),
+    "chain10k": lambda: inputs.chain(10_000),
+    "k1": lambda: inputs.random_mesh(50, 400, 1, 23),
+}
+
+
+def _plan(m, adjoint):
+    from paper_2507_13204_amd import MeshObjective
+    return MeshObjective(to_dev(m.conn), to_dev(m.B), to_dev(m.w), m.n_nodes, adjoint=adjoint)
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_transposed_connectivity_is_bit_exact(name):
+    from paper_2507_13204_amd.pgrad import EXPORT_CSR_INC, EXPORT_CSR_OFFS
+    m = MESHES[name]()
+    if name == "rand_k5_repeats":
+        assert any(len(set(r)) < 5 for r in m.conn[:500])  # repeated nodes inside an element
+    obj = _plan(m, "gather")
+    offs = obj.export(EXPORT_CSR_OFFS)
+    inc = obj.export(EXPORT_CSR_INC)
+    want_offs, want_inc = oracle.mesh_csr(m.n_nodes, m.conn)
+    assert offs.dtype == np.int32 and inc.dtype == np.int32
+    assert np.array_equal(offs, want_offs)
+    assert np.array_equal(inc, want_inc)
+
+
+@pytest.mark.parametrize("name", ["hex17", "hex128", "rand_k5_repeats", "rand_k8_repeats",
+                                  "chain10k", "k1"])
+def test_colour_classes_are_the_greedy_colouring(name):
+    from paper_2507_13204_amd.pgrad import EXPORT_COLOUR_ELEMS, EXPORT_COLOUR_OFFS
+    m = MESHES[name]()
+    obj = _plan(m, "colour")
+    coffs = obj.export(EXPORT_COLOUR_OFFS)
+    elems = obj.export(EXPORT_COLOUR_ELEMS)
+    # every element exactly once, ascending inside its class
+    assert coffs[0] == 0 and coffs[-1] == m.n_elems and np.all(np.diff(coffs) >= 0)
+    assert np.array_equal(np.sort(elems), np.arange(m.n_elems, dtype=np.int32))
+    colour = np.empty(m.n_elems, dtype=np.int32)
+    for c in range(len(coffs) - 1):
+        cls = elems[coffs[c]:coffs[c + 1]]
+        assert np.all(np.diff(cls) > 0)
+        colour[cls] = c
+    assert oracle.colour_conflicts(m.n_nodes, m.conn, colour, len(coffs) - 1) == 0
+    want, nc = oracle.greedy_colour(m.n_nodes, m.conn)
+    assert nc == len(coffs) - 1 == obj.info()["n_colours"]
+    assert np.array_equal(colour, want)
+
+
+def test_structures_absent_from_other_plans_are_refused():
+    from paper_2507_13204_amd.pgrad import EUNSUPPORTED, EXPORT_COLOUR_OFFS, EXPORT_CSR_OFFS, PgError
+    m = inputs.hex_mesh(9, seed=24)
+    atomic = _plan(m, "atomic")
+    for what in (EXPORT_CSR_OFFS, EXPORT_COLOUR_OFFS):
+        with pytest.raises(PgError) as ei:
+            atomic.export(what)
+        assert ei.value.code == EUNSUPPORTED
+    info = atomic.info()
+    assert info["bound"] == 1 and info["lds_slots"] in (2048, 4096) and info["adjoint"] == 1

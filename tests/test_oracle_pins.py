@@ -261,6 +261,61 @@ def test_colour_checker(orc):
     assert orc.colour_conflicts(m.n_nodes, m.conn, (i % 2).astype(np.int32), 2) > 0
 
 
+@pytest.mark.parametrize("mesh", [inputs.hex_mesh(20, seed=4), inputs.random_mesh(500, 1200, 5, 3),
+                                  inputs.chain(1000)], ids=["hex20", "rand_k5", "chain"])
+def test_threaded_oracle_matches_the_plain_one(orc, mesh):
+    """The OpenMP build (timed as the CPU baseline) computes the same f and
+    gradient; only the summation order differs."""
+    f1, g1 = orc.mesh_gradient(mesh.n_nodes, mesh.conn, mesh.B, mesh.w, mesh.x)
+    f2, g2, threads = orc.mesh_gradient_threads(mesh.n_nodes, mesh.conn, mesh.B, mesh.w, mesh.x)
+    assert threads >= 1
+    assert abs(f2 - f1) <= 1e-14 * abs(f1)
+    assert rel(g2, g1) <= 1e-14
+
+
+def _greedy_brute(conn):
+    """The greedy colouring's definition taken literally: for every element,
+    every earlier element, every pair of corners (pure Python, tiny meshes)."""
+    E = conn.shape[0]
+    colour = []
+    for e in range(E):
+        nodes = set(int(v) for v in conn[e])
+        taken = {colour[f] for f in range(e) if nodes & set(int(v) for v in conn[f])}
+        c = 0
+        while c in taken:
+            c += 1
+        colour.append(c)
+    return np.array(colour, dtype=np.int32)
+
+
+@pytest.mark.parametrize("mesh", [inputs.random_mesh(12, 30, 3, 4), inputs.random_mesh(40, 60, 8, 5),
+                                  inputs.random_mesh(6, 15, 5, 6), inputs.hex_mesh(4, seed=2),
+                                  inputs.chain(17)],
+                         ids=["rand_k3", "rand_k8", "rand_k5_repeats", "hex4", "chain"])
+def test_greedy_colour_is_the_definition(orc, mesh):
+    colour, nc = orc.greedy_colour(mesh.n_nodes, mesh.conn)
+    want = _greedy_brute(mesh.conn)
+    assert np.array_equal(colour, want)
+    assert nc == int(want.max()) + 1
+    assert orc.colour_conflicts(mesh.n_nodes, mesh.conn, colour, nc) == 0
+
+
+def test_greedy_colour_of_a_structured_hex_is_the_parity_pattern(orc):
+    """In lexicographic element order the greedy colouring of a structured hex
+    mesh is (i mod 2) + 2 (j mod 2) + 4 (k mod 2): derived by hand for the
+    first row pairs and checked here on a 9^3-node mesh."""
+    s = 9
+    m = inputs.hex_mesh(s, seed=3)
+    idx = np.arange(m.n_elems)
+    i, j, k = idx % (s - 1), (idx // (s - 1)) % (s - 1), idx // (s - 1) ** 2
+    colour, nc = orc.greedy_colour(m.n_nodes, m.conn)
+    assert nc == 8
+    assert np.array_equal(colour, (i % 2 + 2 * (j % 2) + 4 * (k % 2)).astype(np.int32))
+    # a colour bound too small is reported, not truncated
+    with pytest.raises(orc.OracleError):
+        orc.greedy_colour(m.n_nodes, m.conn, max_colours=7)
+
+
 # ------------------------------------------------------------------ dense
 
 def test_dot2_exact_rational(orc):
