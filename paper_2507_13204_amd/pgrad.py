@@ -299,6 +299,13 @@ class _Plan:
                 return pol
         return "recompute"
 
+    def _stores_tape(self) -> bool:
+        """True if the plan's resolved checkpoint is PG_STORE (pg_adjoint
+        then reads the workspace tape of the last pg_objective)."""
+        if getattr(self, "_stores", None) is None:
+            self._stores = self.info()["ckpt"] == STORE
+        return self._stores
+
     def timing(self, mode: int):
         """0 off, 1 time the dominant kernel of each call, 2 time each call."""
         check(lib().pg_timing(self._plan, int(mode)), "pg_timing")
@@ -812,6 +819,11 @@ class _ObjectiveFn(torch.autograd.Function):
         if ctx.policy == "none":
             raise PgError(ESTATE, "backward", "the forward ran without a gradient requested")
         (xd,) = ctx.saved_tensors
+        if ctx.obj._stores_tape():
+            # A PG_STORE plan's adjoint reads the forward values its last
+            # objective call kept in the workspace, which another forward may
+            # have replaced since: record them again for this x first.
+            ctx.obj._objective(xd, _ObjectiveFn._fshape(ctx.obj))
         return ctx.obj.adjoint(xd, fbar), None, None
 
 

@@ -136,18 +136,23 @@ def test_bdense_full_size_f32(bd_full):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_bdense_fn_full_size_fd_16_directions(bd_full, dtype):
     """The autograd form at 4096 x 1024: central differences of the GPU
-    objective on 16 random directions against <G, D>.  FP64: h = 1e-4,
-    1e-6 relative.  FP32: the perturbed points are rounded to FP32, so the
-    difference is taken against the exact step Xp - Xm; h = 1e-2 keeps the
-    FP32 rounding of f(Xp) - f(Xm) near 1e-6 and the third-order term near
-    1e-6 relative; bar 1e-4."""
+    objective on 16 random unit-norm directions against <G, Xp - Xm>.
+    FP64: h = 1e-4, 1e-6 relative.  FP32: the perturbed points are rounded
+    to FP32, so the difference is taken against the exact step Xp - Xm.
+    Each FP32 evaluation of f carries rounding noise that does not shrink
+    with h: the products Y = A X are accurate to about 2^-24 |Y| per entry
+    (|Y| ~ 0.6), and the 4M errors add like a random walk in
+    f = sum W psi(Y), about 2048 * 6e-8 * 0.6 = 7e-5 per evaluation (1.5e-4
+    was seen in f(Xp) - f(Xm) at h = 1e-2, where the slope is only 0.0125).
+    So h = 1: the slope is about 1.2, the noise about 1e-4 of it, and the
+    third-order term about 2e-7 of it ((A D) entries are ~5e-4); bar 1e-3."""
     from paper_2507_13204_amd import BatchedDense, BatchedDenseFn
     b = bd_full
     obj = BatchedDense(to_dev(b.A, dtype), to_dev(b.W, dtype))
     X = to_dev(b.X, dtype).requires_grad_(True)
     BatchedDenseFn.apply(X, obj).backward()
     G = X.grad.double()
-    h, tol = (1e-4, 1e-6) if dtype == torch.float64 else (1e-2, 1e-4)
+    h, tol = (1e-4, 1e-6) if dtype == torch.float64 else (1.0, 1e-3)
     with torch.no_grad():
         for D in inputs.fd_directions(b.X.shape, 16, seed=33):
             Dt = to_dev(D)
