@@ -264,6 +264,35 @@ pg_status pg_adjoint_tape(pg_plan plan, const double* fbar, const void* tape, vo
 pg_status pg_scale(pg_dtype dtype, int64_t n, const double* alpha, const void* x, void* y,
                    pg_stream stream);
 
+/* ------------------------------------------------- allocation-free call
+ *
+ * For callers that cannot allocate device memory or bind a workspace: code
+ * recorded under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation.  The same FP64 gradient as pg_gradient on a mesh plan
+ * with the default options (atomic adjoint combined per workgroup in a
+ * 4096-slot LDS table, 512-thread workgroups, grad overwritten), but with no
+ * plan: grad is cleared by a fill kernel, the element pass scatters into it,
+ * and the per-workgroup partial sums of f go to a fixed device array of
+ * PG_NOALLOC_MAX_WORKGROUPS doubles (512 KiB, one copy per GPU, held until
+ * the process ends) that one more workgroup reduces into f_out in a fixed
+ * order.  Nothing is allocated and nothing waits on the host.
+ *   n_nodes, n_elems >= 0; 1 <= k <= PG_MAX_K; n_nodes < 2^31;
+ *   n_elems * k < 2^31; n_elems <= 512 * PG_NOALLOC_MAX_WORKGROUPS
+ *   (PG_EINVAL otherwise, nothing enqueued).
+ *   conn (int32, n_elems * k), B (n_elems * k), w (n_elems), x (n_nodes):
+ *   device FP64 inputs; grad (n_nodes, device, overwritten) must not overlap
+ *   x or the operands (PG_EALIAS); f_out: device, 1 FP64.
+ * conn is NOT validated (no plan, so no bind-time check): every entry must
+ * lie in [0, n_nodes), as pg_bind_workspace of a mesh plan on the same
+ * connectivity verifies.  Calls on one GPU share its array: calls that
+ * overlap in time on that GPU (two streams) race; calls ordered on one
+ * stream do not.  PG_EHIP if a launch fails. */
+#define PG_NOALLOC_MAX_WORKGROUPS 65536
+pg_status pg_mesh_gradient_noalloc(int64_t n_nodes, int64_t n_elems, int32_t k,
+                                   const int32_t* conn, const double* B, const double* w,
+                                   const double* x, double* grad, double* f_out,
+                                   pg_stream stream);
+
 /* ------------------------------------------------------------ plan queries */
 
 typedef struct {

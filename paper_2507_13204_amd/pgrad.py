@@ -43,7 +43,7 @@ EXPORTS = ("pg_default_options", "pg_mesh_plan", "pg_dense_plan", "pg_bdense_pla
            "pg_prog_gather", "pg_prog_add", "pg_prog_mul", "pg_prog_map", "pg_prog_scan",
            "pg_prog_segment_sum", "pg_prog_broadcast",
            "pg_prog_sum", "pg_prog_fusion", "pg_prog_plan", "pg_prog_bind_workspace", "pg_prog_run",
-           "pg_prog_info", "pg_prog_destroy")
+           "pg_prog_info", "pg_prog_destroy", "pg_mesh_gradient_noalloc")
 MAPS = {"square": 0, "psi": 1}
 
 
@@ -121,6 +121,7 @@ def lib():
     L.pg_scale.argtypes = [ctypes.c_int, _I64, _VP, _VP, _VP, _VP]
     L.pg_plan_info.argtypes = [_VP, ctypes.POINTER(PlanInfo)]
     L.pg_plan_export.argtypes = [_VP, _I32, _VP, ctypes.c_size_t, _SZP]
+    L.pg_mesh_gradient_noalloc.argtypes = [_I64, _I64, _I32, _VP, _VP, _VP, _VP, _VP, _VP, _VP]
     L.pg_plan_destroy.argtypes = [_VP]
     L.pg_timing.argtypes = [_VP, _I32]
     L.pg_timing_read.argtypes = [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]
@@ -159,7 +160,7 @@ def lib():
                  "pg_workspace_size", "pg_bind_workspace", "pg_objective", "pg_gradient",
                  "pg_adjoint", "pg_hvp", "pg_jvp", "pg_timing", "pg_timing_read", "pg_plan_destroy",
                  "pg_tape_bytes", "pg_objective_tape", "pg_adjoint_tape", "pg_scale",
-                 "pg_plan_info", "pg_plan_export",
+                 "pg_plan_info", "pg_plan_export", "pg_mesh_gradient_noalloc",
                  "pg_laplace1d_plan", "pg_laplace1d_objective", "pg_laplace1d_gradient"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -770,6 +771,20 @@ def scale(alpha: torch.Tensor, x: torch.Tensor, out: Optional[torch.Tensor] = No
     check(lib().pg_scale(_dtype_code(x), x.numel(), _ptr(alpha), _ptr(x), _ptr(y),
                          _stream(stream)), "pg_scale")
     return y
+
+
+def mesh_gradient_noalloc(conn: torch.Tensor, B: torch.Tensor, w: torch.Tensor, x: torch.Tensor,
+                          grad: torch.Tensor, f_out: torch.Tensor, stream=None) -> None:
+    """pg_mesh_gradient_noalloc: the FP64 mesh gradient into caller-given grad
+    (n_nodes) and f_out (one float64), with no plan, no workspace and no
+    allocation (the library keeps the partial sums of f in a fixed device
+    array).  conn: (n_elems, k) int32 with entries in [0, n_nodes), which
+    this call does not check."""
+    _need_cuda(conn, B, w, x, grad, f_out)
+    n_elems, k = (conn.shape[0], conn.shape[1]) if conn.dim() == 2 else (conn.numel(), 1)
+    check(lib().pg_mesh_gradient_noalloc(x.numel(), n_elems, k, _ptr(conn), _ptr(B), _ptr(w),
+                                         _ptr(x), _ptr(grad), _ptr(f_out), _stream(stream)),
+          "pg_mesh_gradient_noalloc")
 
 
 def _seed(gout) -> torch.Tensor:
