@@ -200,9 +200,15 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
 def _stream(stream=None):
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ctypes.c_void_p(s.cuda_stream)
+    if stream is None:
+        if _raw_stream is not None:  # the current stream's handle without a Stream object
+            return ctypes.c_void_p(_raw_stream(torch.cuda.current_device()))
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
 
 
 def _need_cuda(*ts):
@@ -788,6 +794,8 @@ def mesh_gradient_noalloc(conn: torch.Tensor, B: torch.Tensor, w: torch.Tensor, 
 
 
 def _seed(gout) -> torch.Tensor:
+    if gout.dtype == torch.float64 and gout.is_contiguous():
+        return gout.detach().reshape(-1)
     return gout.detach().to(torch.float64).contiguous().reshape(-1)
 
 
