@@ -83,10 +83,18 @@ typedef enum {
                           contributions per node in LDS in a fixed order
                           (local incidence lists built at bind), then a
                           node-parallel pass adds the tiles' partials in
-                          tile order; no atomics, no fill of grad.  Mesh
-                          plans only; the workspace is sized for the worst
-                          case (12 + 2 + 4 bytes per incidence more than the
-                          atomic plan). */
+                          tile order; no atomics, no fill of grad.  When
+                          the bind finds that no tile puts one node at one
+                          corner twice and that one slot hash separates
+                          every tile's nodes (structured meshes do), the
+                          per-node sums are built instead in one round per
+                          corner, in ascending corner order, reading no
+                          incidence lists; pg_plan_info reports that form's
+                          slot count in lds_slots (0: the general form).
+                          Mesh plans only; the workspace is sized for the
+                          worst case (12 + 2 + 4 bytes per incidence more
+                          than the atomic plan, or 32 KiB per 512-element
+                          tile if larger). */
 } pg_adjoint_kind;
 
 /* What the forward pass keeps for the reverse pass (section 4: intermediates
@@ -302,7 +310,8 @@ typedef struct {
     int32_t ckpt;          /* resolved pg_ckpt (never PG_CKPT_AUTO) */
     int32_t block;         /* threads per workgroup of the element pass */
     int32_t tile;          /* elements per thread */
-    int32_t lds_slots;     /* LDS table of the combined atomic scatter (0: none; set at bind) */
+    int32_t lds_slots;     /* LDS table of the combined atomic scatter, or of the
+                              tiled adjoint's corner-round form (0: none; set at bind) */
     int32_t one_launch;    /* 1 if every call is one launch */
     int32_t n_colours;     /* colour classes (colour adjoint, after bind), else 0 */
     int32_t bound;         /* 1 after a successful pg_bind_workspace */

@@ -183,6 +183,8 @@ struct pg_plan_s {
     bool small = false;       // each call one launch (small_kernels.hip)
     int tiled_tile = 0;       // elements per tile of the two-level deterministic adjoint
     int64_t tiled_nt = 0;
+    int tiled_round_slots = 0;      // corner-round level 1: slots per tile (0: general form)
+    uint32_t tiled_round_shift = 0; // its slot hash rotation
     size_t n_partials = 0;
     char* ws = nullptr;
     bool bound = false;
@@ -326,7 +328,10 @@ void layout_mesh(pg_plan_s* p) {
         p->o_tbase = L.take(sizeof(int64_t) * (size_t)(p->tiled_nt + 1));
         p->o_loff = L.take(sizeof(int16_t) * (size_t)p->tiled_nt * (size_t)tiled_stride(p));
         p->o_lidx = L.take(sizeof(int16_t) * (size_t)std::max<int64_t>(inc, 1));
-        p->o_stage = L.take(sizeof(double) * (size_t)std::max<int64_t>(inc, 1));
+        // staging: the general form's partials (at most one per incidence) or
+        // the corner-round form's tile * 4096 slots, whichever is larger
+        p->o_stage = L.take(sizeof(double) *
+                            (size_t)std::max<int64_t>(std::max<int64_t>(inc, p->tiled_nt * 4096), 1));
         p->o_noff = L.take(sizeof(int32_t) * (size_t)(m.n_nodes + 1));
         p->o_npos = L.take(sizeof(int32_t) * (size_t)std::max<int64_t>(inc, 1));
     }
@@ -551,6 +556,8 @@ TiledView tiled_view(pg_plan p) {
     v.stage = p->at<double>(p->o_stage);
     v.noff = p->at<int32_t>(p->o_noff);
     v.npos = p->at<int32_t>(p->o_npos);
+    v.round_slots = p->tiled_round_slots;
+    v.round_shift = p->tiled_round_shift;
     return v;
 }
 
@@ -741,6 +748,68 @@ void table_of(const std::vector<std::vector<int32_t>>& tiles, int* slots, uint32
 // per tile its sorted distinct nodes and, per local node, the tile-relative
 // positions of its incidences in ascending order; per node, its staging
 // slots in ascending tile order.
+// Corner-round form of the tiled adjoint's first level (tiled_kernels.hip):
+// usable when k is 2, 4 or 8, tiles have at most 512 elements, inside every
+// tile no two elements put the same node at the same corner, and some slot
+// count S (2048 or 4096) and hash rotation give every tile's distinct nodes
+// distinct slots.  On success *slots, *shift are set and tile_nodes[t] holds
+// tile t's distinct nodes.
+bool rounds_eligible(const std::vector<int32_t>& conn, int64_t E, int k, int T, int64_t N,
+                     std::vector<std::vector<int32_t>>& tile_nodes, int* slots, uint32_t* shift) {
+    if ((k != 2 && k != 4 && k != 8) || T > 512 || E == 0) return false;
+    const int64_t nt = (E + T - 1) / T;
+    if (nt * 4096 >= ((int64_t)1 << 31)) return false;
+    std::vector<int64_t> mark((size_t)N, -1);
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t e0 = t * T, e1 = std::min(E, e0 + T);
+        for (int j = 0; j < k; ++j) {
+            const int64_t stamp = t * k + j;
+            for (int64_t e = e0; e < e1; ++e) {
+                const int32_t n = conn[(size_t)(e * k + j)];
+                if (mark[(size_t)n] == stamp) return false;
+                mark[(size_t)n] = stamp;
+            }
+        }
+    }
+    std::fill(mark.begin(), mark.end(), -1);
+    tile_nodes.assign((size_t)nt, {});
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t e0 = t * T, e1 = std::min(E, e0 + T);
+        auto& v = tile_nodes[(size_t)t];
+        for (int64_t q = e0 * k; q < e1 * k; ++q) {
+            const int32_t n = conn[(size_t)q];
+            if (mark[(size_t)n] != t) {
+                mark[(size_t)n] = t;
+                v.push_back(n);
+            }
+        }
+    }
+    for (int S : {2048, 4096}) {
+        std::vector<int64_t> owner((size_t)S, -1);
+        int64_t stamp = 0;
+        for (uint32_t sh = 1; sh < (uint32_t)S; sh += 2) {
+            bool good = true;
+            for (int64_t t = 0; t < nt && good; ++t, ++stamp) {
+                for (const int32_t n : tile_nodes[(size_t)t]) {
+                    const uint32_t u = (uint32_t)n;
+                    const uint32_t sl = (u + (u >> 12) * sh) & (uint32_t)(S - 1);
+                    if (owner[sl] == stamp) {
+                        good = false;
+                        break;
+                    }
+                    owner[sl] = stamp;
+                }
+            }
+            if (good) {
+                *slots = S;
+                *shift = sh;
+                return true;
+            }
+        }
+    }
+    return false;
+}
+
 pg_status mesh_tiled_build(pg_plan p, hipStream_t s) {
     const MeshView& m = p->mesh;
     const int k = m.k, T = p->tiled_tile;
@@ -749,6 +818,40 @@ pg_status mesh_tiled_build(pg_plan p, hipStream_t s) {
     if (inc > 0) {
         PG_HIP(hipMemcpyAsync(conn.data(), m.conn, sizeof(int32_t) * (size_t)inc, hipMemcpyDeviceToHost, s));
         PG_HIP(hipStreamSynchronize(s));
+    }
+    p->tiled_round_slots = 0;
+    p->tiled_round_shift = 0;
+    {
+        std::vector<std::vector<int32_t>> tile_nodes;
+        int S = 0;
+        uint32_t sh = 0;
+        if (rounds_eligible(conn, E, k, T, N, tile_nodes, &S, &sh)) {
+            // node -> its tiles' staging positions t * S + slot, ascending t
+            std::vector<int32_t> noff((size_t)N + 1, 0);
+            int64_t total = 0;
+            for (const auto& v : tile_nodes) {
+                for (const int32_t n : v) noff[(size_t)n + 1]++;
+                total += (int64_t)v.size();
+            }
+            for (int64_t n = 0; n < N; ++n) noff[(size_t)n + 1] += noff[(size_t)n];
+            std::vector<int32_t> npos((size_t)std::max<int64_t>(total, 1));
+            std::vector<int32_t> fill(noff.begin(), noff.end() - 1);
+            for (int64_t t = 0; t < nt; ++t)
+                for (const int32_t n : tile_nodes[(size_t)t]) {
+                    const uint32_t u = (uint32_t)n;
+                    const uint32_t sl = (u + (u >> 12) * sh) & (uint32_t)(S - 1);
+                    npos[(size_t)fill[(size_t)n]++] = (int32_t)(t * S + sl);
+                }
+            PG_HIP(hipMemcpyAsync(p->at<int32_t>(p->o_noff), noff.data(), sizeof(int32_t) * noff.size(),
+                                  hipMemcpyHostToDevice, s));
+            if (total > 0)
+                PG_HIP(hipMemcpyAsync(p->at<int32_t>(p->o_npos), npos.data(),
+                                      sizeof(int32_t) * (size_t)total, hipMemcpyHostToDevice, s));
+            PG_HIP(hipStreamSynchronize(s));
+            p->tiled_round_slots = S;
+            p->tiled_round_shift = sh;
+            return PG_OK;
+        }
     }
     std::vector<int64_t> tbase((size_t)nt + 1, 0);
     const int ls = tiled_stride(p);
@@ -1633,6 +1736,8 @@ pg_status pg_plan_info(pg_plan p, pg_plan_info_t* info) {
     const bool table = (p->kind == K_MESH || p->kind == K_BATCH) && p->opt.adjoint == PG_ADJ_ATOMIC &&
                        p->opt.scatter != 1;
     r.lds_slots = table && p->bound ? (p->kind == K_BATCH ? 4096 : p->agg_slots) : 0;
+    if (p->kind == K_MESH && p->opt.adjoint == PG_ADJ_TILED && p->bound)
+        r.lds_slots = p->tiled_round_slots;
     r.one_launch = p->small ? 1 : 0;
     r.n_colours = p->colour_off.empty() ? 0 : (int32_t)(p->colour_off.size() - 1);
     r.bound = p->bound ? 1 : 0;

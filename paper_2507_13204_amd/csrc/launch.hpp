@@ -126,6 +126,12 @@ struct TiledView {
     double* stage = nullptr;
     const int32_t* noff = nullptr;
     const int32_t* npos = nullptr;
+    // Corner-round form of level 1 (0: the general form): slots per tile
+    // (2048 or 4096; the tile is then at most 512 elements) and the slot hash
+    // rotation, both chosen at bind; stage then holds n_tiles * round_slots
+    // entries, tile t's at t * round_slots + slot.
+    int round_slots = 0;
+    uint32_t round_shift = 0;
 };
 int tiled_tile_elems(int block, int32_t k);
 // Dynamic LDS of one level-1 workgroup: contributions, positions and offsets.

@@ -11,6 +11,18 @@
 // staging writes are coalesced and no zero fill of grad is needed.  This is
 // the conclusion's "reschedule the reverse threads" remedy applied at the
 // workgroup level, with the workgroup-local reschedule done in LDS.
+//
+// Level 1 has two forms.  The general one reads, with the element rows, the
+// tile's local incidence lists built at bind.  The corner-round form serves
+// connectivities the plan has checked at bind: inside every tile no two
+// elements put the same node at the same corner, and one hash of the node
+// number gives the tile's distinct nodes distinct LDS slots.  Each node's
+// partial is then built in k rounds, round j adding every element's corner-j
+// contribution with a plain read-add-write (no two threads of a round touch
+// one slot), a barrier between rounds: the additions to a slot come in
+// ascending corner order, the same on every run, and no per-incidence data is
+// read.  The partials are stored at stage[tile * slots + slot]; the plan lists
+// each node's positions in ascending tile order for level 2.
 #include "device_common.hpp"
 #include "elem_tile.hpp"
 #include "launch.hpp"
@@ -123,6 +135,76 @@ k_mesh_tiled(MeshView m, MeshPass p, TiledView tv) {
     }
 }
 
+// Corner-round level 1 (see the header): S direct-mapped slots per tile,
+// slot(n) = (n + (n >> 12) * shift) mod S, collision-free in every tile (the
+// plan checked it).  The row loads are issued before the slot table is
+// cleared, as in the element pass.
+template <int S>
+struct RoundTable {
+    int32_t key[S];
+    double val[S];
+};
+
+template <typename T, int K, bool OBJ, int S>
+__global__ void __launch_bounds__(512)
+k_mesh_tiled_rounds(MeshView m, MeshPass p, TiledView tv) {
+    __shared__ RoundTable<S> tab;
+    __shared__ double lds[16];
+    const T* __restrict__ B = static_cast<const T*>(m.B);
+    const T* __restrict__ W = static_cast<const T*>(m.w);
+    const T* __restrict__ X = static_cast<const T*>(p.x);
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t e = t * blockDim.x + threadIdx.x;
+    const bool ok = e < m.n_elems;
+    const double fb = p.fbar ? p.fbar[0] : 1.0;
+    const uint32_t shift = tv.round_shift;
+    int32_t cr[K];
+    T br[K];
+    double wd = 0.0, u = 0.0;
+    if (ok) {
+        load_conn_row<T, K>(m.conn, e, cr);
+        load_b_row<K>(B, e, br);
+        wd = to_f64(W[e]);
+    }
+    for (int q = threadIdx.x; q < S; q += blockDim.x) {
+        tab.key[q] = -1;
+        tab.val[q] = 0.0;
+    }
+    if (ok) {
+        if (p.u_in) {
+            u = p.u_in[e];
+        } else {
+            T xv[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) xv[j] = X[cr[j]];
+#pragma unroll
+            for (int j = 0; j < K; ++j) u += to_f64(br[j]) * to_f64(xv[j]);
+        }
+    }
+    const double s2 = u * u;
+    double tsum = 0.0;
+    if constexpr (OBJ) tsum = wd * psi_from_sq(s2);
+    const double v = fb * wd * dpsi_from(u, s2);
+    __syncthreads();  // the table is clear
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (ok) {
+            const uint32_t n = (uint32_t)cr[j];
+            const uint32_t sl = (n + (n >> 12) * shift) & (uint32_t)(S - 1);
+            tab.val[sl] += v * to_f64(br[j]);
+            tab.key[sl] = cr[j];
+        }
+        __syncthreads();
+    }
+    double* __restrict__ st = tv.stage + t * S;
+    for (int q = threadIdx.x; q < S; q += blockDim.x)
+        if (tab.key[q] >= 0) st[q] = tab.val[q];
+    if constexpr (OBJ) {
+        const double sm = block_sum_dyn(tsum, lds);
+        if (threadIdx.x == 0) p.partials[t] = sm;
+    }
+}
+
 // Slots are taken four at a time so that their loads are in flight together;
 // the additions stay in ascending slot order.
 template <typename T>
@@ -147,8 +229,24 @@ k_node_tiled(int64_t n_nodes, const int32_t* __restrict__ noff, const int32_t* _
     grad[n] = accumulate ? static_cast<T>(to_f64(grad[n]) + s) : static_cast<T>(s);
 }
 
+template <typename T, bool OBJ, int S>
+hipError_t launch_rounds_k(const MeshView& m, const MeshPass& p, const TiledView& tv,
+                           hipStream_t s) {
+    const dim3 grid((unsigned)tv.n_tiles), block(tv.tile);
+    switch (m.k) {
+        case 2: PG_LAUNCH((k_mesh_tiled_rounds<T, 2, OBJ, S>), grid, block, 0, s, m, p, tv); break;
+        case 4: PG_LAUNCH((k_mesh_tiled_rounds<T, 4, OBJ, S>), grid, block, 0, s, m, p, tv); break;
+        case 8: PG_LAUNCH((k_mesh_tiled_rounds<T, 8, OBJ, S>), grid, block, 0, s, m, p, tv); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename T, bool OBJ>
 hipError_t launch_tiled_t(const MeshView& m, const MeshPass& p, const TiledView& tv, hipStream_t s) {
+    if (tv.round_slots == 2048) return launch_rounds_k<T, OBJ, 2048>(m, p, tv, s);
+    if (tv.round_slots == 4096) return launch_rounds_k<T, OBJ, 4096>(m, p, tv, s);
+    if (tv.round_slots != 0) return hipErrorInvalidValue;
     const dim3 grid((unsigned)tv.n_tiles), block(tv.tile);
     const size_t shmem = tiled_lds_bytes(tv.tile, m.k);
     switch (m.k) {

@@ -382,6 +382,28 @@ def test_tiled_adjoint_tile_sizes(name, block):
     assert rel(g2.cpu().numpy(), 2.0 * g.cpu().numpy()) <= 1e-15
 
 
+@pytest.mark.parametrize("name,rounds", [("hex23", True), ("hex17", True), ("chain10k", True),
+                                         ("rand_k8", False), ("rand_k4", False), ("rand_k5", False)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_tiled_adjoint_forms(name, rounds, dtype):
+    """The plan takes the corner-round first level (reported as its slot
+    count in lds_slots) where every tile puts distinct nodes at each corner
+    and one slot hash separates each tile's nodes -- the structured meshes --
+    and the general one (lds_slots 0) for random connectivity or k = 5.  Both
+    match the oracle and repeat bit for bit."""
+    m = MESHES[name]()
+    obj, x = _obj(m, dtype, adjoint="tiled", block=512)
+    info = obj.info()
+    assert (info["lds_slots"] in (2048, 4096)) if rounds else info["lds_slots"] == 0, info
+    outs = [obj.gradient(x) for _ in range(3)]
+    _check(m, outs[0][0].item(), outs[0][1].cpu().numpy(), dtype)
+    for f, g in outs[1:]:
+        assert f.item() == outs[0][0].item()
+        assert torch.equal(g, outs[0][1])
+    fbar = torch.tensor([-2.0], dtype=torch.float64, device="cuda")
+    _check(m, None, obj.adjoint(x, fbar).cpu().numpy(), dtype, fbar=-2.0)
+
+
 @pytest.mark.parametrize("name", ["chain10k", "hex17", "hex23", "rand_k8", "rand_k4"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_one_launch_small_meshes(name, dtype):
