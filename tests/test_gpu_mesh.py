@@ -404,6 +404,22 @@ def test_tiled_adjoint_forms(name, rounds, dtype):
     _check(m, None, obj.adjoint(x, fbar).cpu().numpy(), dtype, fbar=-2.0)
 
 
+def test_tiled_corner_rounds_with_a_repeated_node_per_element():
+    """Every element's corner 1 collapsed onto its corner 0: each corner still
+    holds distinct nodes across a tile's elements, so the plan keeps the
+    corner-round form, and a node then receives one element's two
+    contributions in rounds 0 and 1 from the same thread."""
+    m = inputs.hex_mesh(23, seed=43)
+    m.conn = np.ascontiguousarray(m.conn.copy())
+    m.conn[:, 1] = m.conn[:, 0]
+    for adj in ("tiled", "atomic"):
+        obj, x = _obj(m, adjoint=adj)
+        if adj == "tiled":
+            assert obj.info()["lds_slots"] in (2048, 4096)
+        f, g = obj.gradient(x)
+        _check(m, f.item(), g.cpu().numpy())
+
+
 @pytest.mark.parametrize("name", ["chain10k", "hex17", "hex23", "rand_k8", "rand_k4"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_one_launch_small_meshes(name, dtype):
