@@ -756,33 +756,29 @@ void table_of(const std::vector<std::vector<int32_t>>& tiles, int* slots, uint32
 // tile t's distinct nodes.
 bool rounds_eligible(const std::vector<int32_t>& conn, int64_t E, int k, int T, int64_t N,
                      std::vector<std::vector<int32_t>>& tile_nodes, int* slots, uint32_t* shift) {
+    (void)N;
     if ((k != 2 && k != 4 && k != 8) || T > 512 || E == 0) return false;
     const int64_t nt = (E + T - 1) / T;
     if (nt * 4096 >= ((int64_t)1 << 31)) return false;
-    std::vector<int64_t> mark((size_t)N, -1);
+    // Per tile, by sorting (memory of one tile, whatever the node count):
+    // each corner's nodes distinct, then the tile's distinct nodes.
+    tile_nodes.assign((size_t)nt, {});
+    std::vector<int32_t> col;
     for (int64_t t = 0; t < nt; ++t) {
         const int64_t e0 = t * T, e1 = std::min(E, e0 + T);
         for (int j = 0; j < k; ++j) {
-            const int64_t stamp = t * k + j;
-            for (int64_t e = e0; e < e1; ++e) {
-                const int32_t n = conn[(size_t)(e * k + j)];
-                if (mark[(size_t)n] == stamp) return false;
-                mark[(size_t)n] = stamp;
+            col.clear();
+            for (int64_t e = e0; e < e1; ++e) col.push_back(conn[(size_t)(e * k + j)]);
+            std::sort(col.begin(), col.end());
+            if (std::adjacent_find(col.begin(), col.end()) != col.end()) {
+                tile_nodes.clear();
+                return false;
             }
         }
-    }
-    std::fill(mark.begin(), mark.end(), -1);
-    tile_nodes.assign((size_t)nt, {});
-    for (int64_t t = 0; t < nt; ++t) {
-        const int64_t e0 = t * T, e1 = std::min(E, e0 + T);
         auto& v = tile_nodes[(size_t)t];
-        for (int64_t q = e0 * k; q < e1 * k; ++q) {
-            const int32_t n = conn[(size_t)q];
-            if (mark[(size_t)n] != t) {
-                mark[(size_t)n] = t;
-                v.push_back(n);
-            }
-        }
+        v.assign(conn.begin() + e0 * k, conn.begin() + e1 * k);
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
     }
     for (int S : {2048, 4096}) {
         std::vector<int64_t> owner((size_t)S, -1);
