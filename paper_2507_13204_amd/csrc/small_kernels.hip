@@ -45,6 +45,7 @@ k_mesh_small(MeshView m, MeshPass p, SmallPass sp) {
     double s = 0.0;
     if constexpr (has_sum(MODE)) s = block_sum_dyn(tsum, lds);
     __syncthreads();
+    static_assert(kSmallMaxRanges < kWave - 1, "the ticket lane must not take a range");
     __shared__ int fin[kSmallMaxRanges];
     __shared__ int any_fin;
     int r0 = 0, nr = 0;
@@ -56,6 +57,12 @@ k_mesh_small(MeshView m, MeshPass p, SmallPass sp) {
         if constexpr (has_sum(MODE))
             if (threadIdx.x == 0) p.partials[lb] = s;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // The ticket (last lane; a workgroup has at most kSmallMaxRanges < 63
+        // ranges) and the range counts (lanes 0 .. nr-1) are taken in the same
+        // batch of atomics, so the workgroup waits for one round trip, not two.
+        int ticket = 0;
+        if constexpr (has_sum(MODE))
+            if (threadIdx.x == kWave - 1) ticket = atomicAdd(sp.ticket, 1);
         if constexpr (is_atomic(MODE)) {
             bool mine = false;
             if ((int)threadIdx.x < nr) {
@@ -67,7 +74,7 @@ k_mesh_small(MeshView m, MeshPass p, SmallPass sp) {
             if (threadIdx.x == 0) any_fin = any;
         }
         if constexpr (has_sum(MODE))
-            if (threadIdx.x == 0) last = atomicAdd(sp.ticket, 1) == (int)gridDim.x - 1;
+            if (threadIdx.x == kWave - 1) last = ticket == (int)gridDim.x - 1;
     }
     __syncthreads();
     if constexpr (is_atomic(MODE)) {
