@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 keys of the hex line")
+    ap.add_argument("--no-other", action="store_true",
+                    help="skip the dense and batched-dense summaries of the hex line")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-vs-per-instance keys of the hex line")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -282,6 +284,9 @@ def bench_hex(args):
     if not args.no_batch:
         out["batch"] = _batch_vs_per_instance(args)
         _progress("batch done")
+    if not args.no_other:
+        out.update(_other_configs(args))
+        _progress("dense and batched dense done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(m, args.cpu_seconds, gbytes)
 
@@ -462,6 +467,64 @@ def _batch_vs_per_instance(args):
             "per_instance_GBps": round(gbytes / (ms_pi * 1e-3), 2),
             "batched_over_per_instance_speedup": round(ms_pi / ms_b, 3),
             "algorithmic_bytes": int(gbytes * 1e9)}
+
+
+def _other_configs(args):
+    """The dense row reduction (10^4 x 10^4, FP64) and the batched dense
+    products (4096^2 by 4096 x 1024, FP64 and FP32 matrix cores) in the hex
+    line: times per call, the dominant kernel from the event hook against its
+    roofline, and the gradient / objective ratios."""
+    import torch
+    from paper_2507_13204_amd import BatchedDense, DenseObjective, inputs
+    dev = torch.device("cuda:0")
+    steps, warm = 10, 3
+    res = {}
+    n = args.dense_n
+    d = inputs.dense(n)
+    A = torch.from_numpy(d.A).to(dev)
+    w = torch.from_numpy(d.w).to(dev)
+    x = torch.from_numpy(d.x).to(dev)
+    obj = DenseObjective(A, w)
+    g = torch.empty_like(x)
+    ms_g = _timed(lambda: obj.gradient(x, out=g), steps, warm)
+    ms_f = _timed(lambda: obj.objective(x), steps, warm)
+    k_g = _hook_ms(obj, lambda: obj.gradient(x, out=g), steps)
+    gbytes = (n * n + 3 * n) * 8 / 1e9
+    res["dense"] = {"workload": f"dense {n}x{n} f64, one pass over A for f and the gradient",
+                    "gradient_ms": round(ms_g, 5), "objective_ms": round(ms_f, 5),
+                    "gradient_over_objective": round(ms_g / ms_f, 4),
+                    "GBps": round(gbytes / (ms_g * 1e-3), 2),
+                    "kernel": "k_dense_fused", "kernel_ms": round(k_g, 5),
+                    "kernel_frac_hbm_peak": round(gbytes / (k_g * 1e-3) / PEAK_HBM_GBS, 4)}
+    obj.close()
+    del A, w, x, g, d
+    torch.cuda.empty_cache()
+    m_, n_ = args.bd_m, args.bd_n
+    b = inputs.batched_dense(m_, n_)
+    flop = 2.0 * m_ * m_ * n_
+    for dt, tdt, peak in (("f64", torch.float64, 78.6), ("f32", torch.float32, 157.3)):
+        A = torch.from_numpy(b.A).to(dev, tdt)
+        W = torch.from_numpy(b.W).to(dev, tdt)
+        X = torch.from_numpy(b.X).to(dev, tdt)
+        o = BatchedDense(A, W, ckpt="store")
+        G = torch.empty_like(X)
+        fbar = torch.ones(1, dtype=torch.float64, device=dev)
+        ms_f = _timed(lambda: o.objective(X), steps, warm)
+        ms_b = _timed(lambda: o.adjoint(X, fbar, out=G), steps, warm)
+        ms_g = _timed(lambda: o.gradient(X, out=G), steps, warm)
+        k_f = _hook_ms(o, lambda: o.objective(X), steps)
+        res[f"bdense_{dt}"] = {
+            "workload": f"batched dense A {m_}x{m_}, X {m_}x{n_}, {dt} matrix cores"
+                        + (", each 16-deep k-tile added into FP64" if dt == "f32" else ""),
+            "forward_kernel_ms": round(k_f, 5),
+            "forward_TFLOPs": round(flop / (k_f * 1e-3) / 1e12, 3),
+            "forward_frac_peak": round(flop / (k_f * 1e-3) / 1e12 / peak, 4),
+            "peak_TFLOPs": peak, "gradient_ms": round(ms_g, 5),
+            "fwd_plus_bwd_over_fwd": round((ms_f + ms_b) / ms_f, 4)}
+        o.close()
+        del A, W, X, G
+        torch.cuda.empty_cache()
+    return res
 
 
 def _timed(fn, steps, warmup):
