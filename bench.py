@@ -286,7 +286,8 @@ def bench_hex(args):
         _progress("batch done")
     if not args.no_other:
         out.update(_other_configs(args))
-        _progress("dense and batched dense done")
+        out.update(_small_sweeps(args))
+        _progress("dense, batched dense and the small sweeps done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(m, args.cpu_seconds, gbytes)
 
@@ -525,6 +526,48 @@ def _other_configs(args):
         del A, W, X, G
         torch.cuda.empty_cache()
     return res
+
+
+def _small_sweeps(args):
+    """The launch-bound cases on a coarse grid of sizes: the 1D chain through
+    the mesh path and the paper's own example (gather schedule, gradients in
+    x and b), gradient / objective wall-clock ratios per size."""
+    import numpy as np
+    import torch
+    from paper_2507_13204_amd import Laplace1D, MeshObjective, inputs
+    dev = torch.device("cuda:0")
+    steps, warm = 20, 5
+    sizes = [1, 100, 1000, 2000, 4000, 6000, 8000, 10_000]
+    chain, paper = [], []
+    for n in sizes:
+        if n >= 2:
+            m = inputs.chain(n)
+            obj = MeshObjective(torch.from_numpy(m.conn).to(dev), torch.from_numpy(m.B).to(dev),
+                                torch.from_numpy(m.w).to(dev), n)
+            x = torch.from_numpy(m.x).to(dev)
+            g = torch.empty_like(x)
+            f = torch.empty((), dtype=torch.float64, device=dev)
+            ms_g = _timed(lambda: obj.gradient(x, out=g, f_out=f), steps, warm)
+            ms_f = _timed(lambda: obj.objective(x, f_out=f), steps, warm)
+            chain.append((n, round(ms_f * 1e3, 3), round(ms_g * 1e3, 3), round(ms_g / ms_f, 4)))
+            obj.close()
+        rng = np.random.default_rng(n)
+        x = torch.from_numpy(rng.uniform(-1, 1, n)).to(dev)
+        b = torch.from_numpy(rng.uniform(-1, 1, n)).to(dev)
+        lp = Laplace1D(n)
+        gx, gb = torch.empty_like(x), torch.empty_like(b)
+        f = torch.empty((), dtype=torch.float64, device=dev)
+        ms_g = _timed(lambda: lp.gradient(x, b, gx=gx, gb=gb, f_out=f), steps, warm)
+        ms_f = _timed(lambda: lp.objective(x, b, f_out=f), steps, warm)
+        paper.append((n, round(ms_f * 1e3, 3), round(ms_g * 1e3, 3), round(ms_g / ms_f, 4)))
+        lp.close()
+    return {"chain": {"workload": "1D chain through the mesh path, n nodes",
+                      "n_us_f_us_grad_ratio": chain,
+                      "max_ratio": max(r[3] for r in chain)},
+            "paper_example": {"workload": "the paper's ||A(3x) - b||^2, dim(x) = n, gradients in x and b",
+                              "n_us_f_us_grad_ratio": paper,
+                              "max_ratio": max(r[3] for r in paper),
+                              "paper_us_f_grad": PAPER_US}}
 
 
 def _timed(fn, steps, warmup):
