@@ -650,9 +650,12 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
             slot += mesh_blocks(q.elist_n, q.block, k_in_registers(m.k) ? q.ept : 1);
         }
         PG_HIP(tmark(p, 1, false, s));
-        if (f32)
+        if (f32 && obj && f_out)  // the conversion's first workgroup also sums f
+            PG_HIP(launch_f64_to_f32_sum(q.gacc, static_cast<float*>(grad), m.n_nodes, acc, 1,
+                                         q.partials, slot, f_out, s));
+        else if (f32)
             PG_HIP(launch_f64_to_f32(q.gacc, static_cast<float*>(grad), m.n_nodes, acc, 1, s));
-        if (obj && f_out) PG_HIP(launch_final_sum(q.partials, slot, f_out, s));
+        if (!f32 && obj && f_out) PG_HIP(launch_final_sum(q.partials, slot, f_out, s));
         return PG_OK;
     }
     if (p->opt.adjoint == PG_ADJ_TILED) {
@@ -683,9 +686,12 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
         PG_HIP(tkern(p, true));
         PG_HIP(launch_mesh_elem(m, obj ? M_GRAD_ATOMIC : M_ADJ_ATOMIC, q, s));
         PG_HIP(tkern(p, false));
-        if (f32)
+        if (f32 && obj && f_out)  // the conversion's first workgroup also sums f
+            PG_HIP(launch_f64_to_f32_sum(q.gacc, static_cast<float*>(grad), m.n_nodes, acc, 1,
+                                         q.partials, p->mesh_blocks_n, f_out, s));
+        else if (f32)
             PG_HIP(launch_f64_to_f32(q.gacc, static_cast<float*>(grad), m.n_nodes, acc, 1, s));
-        if (obj && f_out) PG_HIP(launch_final_sum(q.partials, p->mesh_blocks_n, f_out, s));
+        if (!f32 && obj && f_out) PG_HIP(launch_final_sum(q.partials, p->mesh_blocks_n, f_out, s));
         return PG_OK;
     }
     if (obj && f_out) PG_HIP(launch_final_sum(q.partials, p->mesh_blocks_n, f_out, s));

@@ -162,6 +162,10 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // dst (FP32) (=|+=) src (FP64); clear: src is zeroed as it is read.
 hipError_t launch_f64_to_f32(double* src, float* dst, int64_t n, int accumulate, int clear,
                              hipStream_t s);
+// The same conversion, and f_out[0] = the fixed-order sum of partials[0..np)
+// (k_final_sum's order) from the first workgroup: one launch instead of two.
+hipError_t launch_f64_to_f32_sum(double* src, float* dst, int64_t n, int accumulate, int clear,
+                                 const double* partials, int64_t np, double* f_out, hipStream_t s);
 // dst (FP64) += src (FP64).
 hipError_t launch_add_f64(const double* src, double* dst, int64_t n, hipStream_t s);
 // y = alpha[0] * x (n entries of dt; FP64 product, rounded once; y may alias x).

@@ -69,12 +69,20 @@ __global__ void __launch_bounds__(256) k_zero1(uint8_t* __restrict__ p, int64_t 
 
 // dst (FP32) (=|+=) src (FP64); with clear, src is left zero for the next call.
 __global__ void __launch_bounds__(256)
-k_f64_to_f32(double* __restrict__ src, float* __restrict__ dst, int64_t n, int accumulate, int clear) {
+k_f64_to_f32(double* __restrict__ src, float* __restrict__ dst, int64_t n, int accumulate, int clear,
+             const double* __restrict__ partials, int64_t np, double* __restrict__ f_out) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const double v = src[i];
         if (clear) src[i] = 0.0;
         dst[i] = accumulate ? static_cast<float>((double)dst[i] + v) : static_cast<float>(v);
+    }
+    // Workgroup 0 also sums the objective's partials in the fixed order of
+    // k_final_sum, saving the reduction its own launch.
+    if (f_out && blockIdx.x == 0) {
+        __shared__ double lds[16];
+        const double s = block_sum_dyn(strided_sum(partials, 0, np), lds);
+        if (threadIdx.x == 0) f_out[0] = s;
     }
 }
 
@@ -261,7 +269,14 @@ hipError_t launch_f64_to_f32(double* src, float* dst, int64_t n, int accumulate,
                              hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_f64_to_f32, dim3(stream_grid(n, 256 * 4, 8192)), dim3(256), 0, s, src,
-                       dst, n, accumulate, clear);
+                       dst, n, accumulate, clear, nullptr, (int64_t)0, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_f64_to_f32_sum(double* src, float* dst, int64_t n, int accumulate, int clear,
+                                 const double* partials, int64_t np, double* f_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_f64_to_f32, dim3(stream_grid(n, 256 * 4, 8192)), dim3(256), 0, s, src,
+                       dst, n, accumulate, clear, partials, np, f_out);
     return hipGetLastError();
 }
 
