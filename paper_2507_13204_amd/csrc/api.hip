@@ -76,9 +76,13 @@ constexpr size_t NONE = ~size_t(0);
 
 namespace pg {
 
-// Candidate rotations of the LDS table hash, spread over the 4096 slots.
-static const uint32_t kShiftCandidates[] = {2533, 1237, 3371, 615, 1861, 2967, 347, 3779, 1493, 2207,
-                                            3061, 881};
+// Candidate parameters of the LDS table hash (agg_slot), tried in this order;
+// the first that gives the sampled workgroups no probes is taken.
+static const uint32_t kShiftCandidates[] = {256, 640, 384, 896, 160, 1152, 96, 1664,
+                                            512, 2304, 200, 3000, 320, 1400, 768, 2600,
+                                            48, 1800, 1024, 3500, 136, 450, 1300, 2048};
+// Workgroups sampled per mesh (or per instance of a batch) to choose it.
+constexpr int kHashSamples = 64;
 
 // Probe count of an S-slot table with rotation `shift` on the sampled tiles
 // (an insert that finds no slot within kProbe steps counts 4 * kProbe: it
@@ -94,7 +98,7 @@ int64_t table_cost(const int32_t* const* tiles, const int64_t* counts, int64_t n
         for (int64_t q = 0; q < counts[t]; ++q) {
             const int32_t n = tiles[t][q];
             const uint32_t u = (uint32_t)n;
-            uint32_t h = (u + (u >> 12) * shift) & mask;
+            uint32_t h = agg_slot(u, shift, (uint32_t)slots);
             int probe = 0;
             while (probe < kProbe && key[h] != -1 && key[h] != n) {
                 h = (h + 1) & mask;
@@ -121,6 +125,7 @@ uint32_t choose_hash_shift(const int32_t* const* tiles, const int64_t* counts, i
             best_cost = cost;
             best = cand;
         }
+        if (best_cost == 0) break;
     }
     if (cost_out) *cost_out = best_cost;
     return best;
@@ -153,7 +158,7 @@ struct pg_plan_s {
     // mesh / batch
     MeshView mesh;
     int64_t mesh_blocks_n = 0;
-    uint32_t hash_shift = 2533;  // LDS table hash parameter chosen at bind time
+    uint32_t hash_shift = kHashRotDefault;  // LDS table hash parameter chosen at bind time
     int agg_slots = 4096;        // LDS table size chosen at bind time
     // colour classes: elements of colour c are elist[colour_off[c] .. colour_off[c+1])
     std::vector<int64_t> colour_off;
@@ -374,7 +379,7 @@ void layout_batch(pg_plan_s* p) {
             const int64_t first = in.elem_off + t * te;
             p->h_tiles.push_back(first);
             p->h_tiles.push_back(std::min(first + te, in.elem_off + in.n_elems));
-            p->h_tiles.push_back(in.node_off | ((int64_t)2533 << 40));
+            p->h_tiles.push_back(in.node_off | ((int64_t)kHashRotDefault << 40));
             p->h_tiles.push_back(((int64_t)oi << 40) | (p->h_seg[oi] + t));
         }
     }
@@ -700,33 +705,43 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
 
 // ------------------------------------------------- LDS table hash choice
 
-// Node numbers touched by elements [e0, e1) of a connectivity (k per row),
-// offset by noff, copied from the device.
-pg_status sample_nodes(const int32_t* conn, int64_t e0, int64_t e1, int32_t k, int64_t noff,
-                       std::vector<int32_t>& out, hipStream_t s) {
-    out.resize((size_t)((e1 - e0) * k));
-    if (out.empty()) return PG_OK;
-    PG_HIP(hipMemcpyAsync(out.data(), conn + e0 * k, sizeof(int32_t) * out.size(),
-                          hipMemcpyDeviceToHost, s));
-    PG_HIP(hipStreamSynchronize(s));
-    if (noff)
-        for (auto& v : out) v = (int32_t)(v + noff);
-    return PG_OK;
-}
-
-// Sampled tiles of one mesh: up to `want` workgroup tiles spread evenly.
+// Sampled tiles of one mesh: every tile when there are at most `want`,
+// else `want` tiles at a fixed stride (tile i * stride), fetched with one
+// strided copy (plus one for a ragged last tile).
 pg_status sample_mesh_tiles(const int32_t* conn, int64_t n_elems, int32_t k, int64_t noff,
                             int64_t span, int want, std::vector<std::vector<int32_t>>& tiles,
                             hipStream_t s) {
     const int64_t nt = (n_elems + span - 1) / span;
-    const int64_t ns = std::min<int64_t>(nt, want);
-    for (int64_t i = 0; i < ns; ++i) {
-        const int64_t t = nt > 1 ? i * (nt - 1) / std::max<int64_t>(ns - 1, 1) : 0;
-        tiles.emplace_back();
-        pg_status st = sample_nodes(conn, t * span, std::min(n_elems, (t + 1) * span), k, noff,
-                                    tiles.back(), s);
-        if (st) return st;
+    if (nt == 0) return PG_OK;
+    const size_t first = tiles.size();
+    const int64_t row = span * k;  // entries per full tile
+    std::vector<int32_t> buf;
+    int64_t stride = 1, ns = nt;
+    if (nt > want) {
+        stride = std::max<int64_t>(1, (nt - 1) / std::max(want - 1, 1));
+        ns = want;
     }
+    // tiles i * stride for i < ns; all full except possibly tile nt - 1
+    const bool ragged_last = (ns - 1) * stride == nt - 1 && n_elems % span != 0;
+    const int64_t nfull = ragged_last ? ns - 1 : ns;
+    buf.resize((size_t)(nfull * row + (ragged_last ? (n_elems - (nt - 1) * span) * k : 0)));
+    if (nfull > 0) {
+        const size_t w = sizeof(int32_t) * (size_t)row;
+        PG_HIP(hipMemcpy2DAsync(buf.data(), w, conn, w * (size_t)stride, w, (size_t)nfull,
+                                hipMemcpyDeviceToHost, s));
+    }
+    if (ragged_last)
+        PG_HIP(hipMemcpyAsync(buf.data() + nfull * row, conn + (nt - 1) * row,
+                              sizeof(int32_t) * (size_t)((n_elems - (nt - 1) * span) * k),
+                              hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < ns; ++i) {
+        const int64_t len = (i < nfull) ? row : (int64_t)buf.size() - nfull * row;
+        tiles.emplace_back(buf.begin() + i * row, buf.begin() + i * row + len);
+    }
+    if (noff)
+        for (size_t i = first; i < tiles.size(); ++i)
+            for (auto& v : tiles[i]) v = (int32_t)(v + noff);
     return PG_OK;
 }
 
@@ -1016,7 +1031,7 @@ pg_status mesh_bind(pg_plan p, hipStream_t s) {
     if (p->opt.scatter != 1 && m.n_elems > 0) {
         std::vector<std::vector<int32_t>> tiles;
         pg_status hst = sample_mesh_tiles(m.conn, m.n_elems, m.k, 0,
-                                          (int64_t)p->opt.block * p->opt.tile, 24, tiles, s);
+                                          (int64_t)p->opt.block * p->opt.tile, kHashSamples, tiles, s);
         if (hst != PG_OK) return hst;
         table_of(tiles, &p->agg_slots, &p->hash_shift);
         if (p->opt.scatter >= 2) {  // the caller fixed the table size
@@ -1067,13 +1082,13 @@ pg_status batch_bind(pg_plan p, hipStream_t s) {
     // LDS table hash parameter per instance, written into its tile records.
     const int64_t nt = p->batch.n_tiles, ni = (int64_t)p->inst.size();
     if (p->opt.scatter != 1) {
-        std::vector<uint32_t> shift((size_t)ni, 2533u);
+        std::vector<uint32_t> shift((size_t)ni, kHashRotDefault);
         for (int64_t i = 0; i < ni; ++i) {
             const pg_instance& in = p->inst[(size_t)i];
             if (in.n_elems == 0) continue;
             std::vector<std::vector<int32_t>> tiles;
             pg_status hst = sample_mesh_tiles(p->batch.conn + in.elem_off * p->batch.k, in.n_elems,
-                                              p->batch.k, in.node_off, p->batch.tile_elems, 4,
+                                              p->batch.k, in.node_off, p->batch.tile_elems, kHashSamples,
                                               tiles, s);
             if (hst != PG_OK) return hst;
             shift[(size_t)i] = shift_of(tiles);

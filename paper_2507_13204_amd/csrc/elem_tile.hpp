@@ -111,16 +111,13 @@ struct AggTableT {
 };
 using AggTable = AggTableT<kAggSlots>;
 
-// Consecutive node numbers go to consecutive slots (so the flush touches few
-// cache lines per instruction); each further window of 4096 node numbers is
-// rotated by `shift` slots, so ranges that are a plane (or an instance) apart
-// in the numbering land on different slots.  The plan picks `shift` (and the
-// table size) for its connectivity by simulating the table on sampled
-// workgroups.
+// Home slot of node n (agg_slot: consecutive numbers in consecutive slots,
+// runs a distance D apart about D * (1 + rot / 4096) slots apart).  The plan picks
+// rot (and the table size) for its connectivity by simulating the table on
+// sampled workgroups.
 template <int S>
-__device__ __forceinline__ uint32_t agg_hash(int32_t n, uint32_t shift) {
-    const uint32_t u = (uint32_t)n;
-    return (u + (u >> 12) * shift) & (S - 1);
+__device__ __forceinline__ uint32_t agg_hash(int32_t n, uint32_t rot) {
+    return agg_slot((uint32_t)n, rot, (uint32_t)S);
 }
 
 template <int S>

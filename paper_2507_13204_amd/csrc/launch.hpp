@@ -60,6 +60,25 @@ struct MeshView {
     const void* w = nullptr;
 };
 
+// Slot of node number u in an S-slot LDS combining table (S a power of two,
+// 64 to 4096).  Node numbers are taken in blocks of 64; block b = u / 64 goes
+// to slot block b + floor(b * rot / 4096) (wrapped), the node to the same
+// place inside it.  So consecutive node numbers take consecutive slots (a
+// whole block of 64 slots is skipped every 4096 / rot blocks, which keeps a
+// wave's 64 lanes on 64 consecutive LDS banks and a flush instruction on few
+// cache lines), and two runs of numbers a distance D apart land about
+// D * (1 + rot / 4096) slots apart whatever their alignment: the plan picks
+// rot (1 <= rot < 4096) so that the runs one workgroup touches (the node rows
+// of neighbouring planes of a structured mesh, say) do not overlap.
+// floor(b * rot / 4096) is taken as (b >> 12) * rot + ((b mod 4096) * rot >> 12)
+// in 32-bit arithmetic.  The kernels and the plan's simulation of the table
+// share this definition.
+__host__ __device__ inline uint32_t agg_slot(uint32_t u, uint32_t rot, uint32_t S) {
+    const uint32_t r = rot & 4095u, b = u >> 6;
+    return (u + 64u * ((b >> 12) * r + (((b & 4095u) * r) >> 12))) & (S - 1);
+}
+constexpr uint32_t kHashRotDefault = 320;  // used where no plan has chosen one
+
 struct MeshPass {
     const void* x = nullptr;       // node values (dtype)
     const void* xd = nullptr;      // direction for M_HVP (dtype)
@@ -75,7 +94,7 @@ struct MeshPass {
     int block = 256;
     int ept = 1;
     int combine = 1;               // combine atomic contributions in LDS first
-    uint32_t hash_shift = 2533;    // LDS table hash parameter (see choose_hash_shift)
+    uint32_t hash_shift = kHashRotDefault;  // LDS table hash parameter (see agg_slot)
     int agg_slots = 4096;          // LDS table size: 4096 or 2048 (see choose_hash_shift)
 };
 
@@ -368,7 +387,7 @@ struct GroupDev {
     const double* gB = nullptr;
     const double* gsrc = nullptr;
     double* gsrc_shadow = nullptr;
-    uint32_t hash_shift = 2533;
+    uint32_t hash_shift = kHashRotDefault;
     int agg_slots = 4096;  // LDS table of the fused gather's scatter: 4096 or 2048
     const double* seed = nullptr;  // device seed of f (nullptr means 1)
     const double* leaf[kGLeaves] = {};

@@ -75,7 +75,7 @@ struct Group {
     bool export_gather = false;  // a gather of its own: no ops, its value written out
     bool sealed = false, has_sum = false;
     int32_t pos = 0;      // schedule position: its last member (the end for a sum-only group)
-    uint32_t hash_shift = 2533;
+    uint32_t hash_shift = kHashRotDefault;
     int agg_slots = 4096;
 };
 
@@ -674,7 +674,7 @@ pg_status pg_prog_bind_workspace(pg_prog p, void* ws, size_t bytes) {
         if (g.gather < 0) continue;
         const Op& op = p->ops[(size_t)g.gather];
         const int64_t span = kGroupBlockScatter, nt = (op.n + span - 1) / span;
-        const int64_t ns = std::min<int64_t>(nt, 24);
+        const int64_t ns = std::min<int64_t>(nt, 64);
         std::vector<std::vector<int32_t>> tiles;
         for (int64_t q = 0; q < ns; ++q) {
             const int64_t t = nt > 1 ? q * (nt - 1) / std::max<int64_t>(ns - 1, 1) : 0;
