@@ -50,8 +50,8 @@ k_batch_tiles(BatchView bv, BatchPass p) {
     if constexpr (has_rev(MODE)) fb = p.fbar ? p.fbar[inst] : 1.0;
     TileArgs a{bv.conn, bv.B, bv.w, p.x, nullptr, p.u_in, p.u_store, nullptr,
                static_cast<double*>(p.grad), nullptr, (uint32_t)(cur.shift_noff >> 40)};
-    const double tsum = elem_tile<T, K, MODE, EPT, AGG>(a, cur.first, cur.end,
-                                                        cur.shift_noff & kNoffMask, fb, tab);
+    const double tsum = elem_tile<T, K, MODE, EPT, AGG, false>(a, cur.first, cur.end,
+                                                               cur.shift_noff & kNoffMask, fb, tab);
     if constexpr (has_obj(MODE)) {
         const double s = block_sum_dyn(tsum, lds);
         if (threadIdx.x == 0) p.partials[cur.slot_inst & kSlotMask] = s;

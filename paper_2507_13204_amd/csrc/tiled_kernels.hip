@@ -137,8 +137,7 @@ k_mesh_tiled(MeshView m, MeshPass p, TiledView tv) {
 
 // Corner-round level 1 (see the header): S direct-mapped slots per tile,
 // slot(n) = (n + (n >> 12) * shift) mod S, collision-free in every tile (the
-// plan checked it).  The row loads are issued before the slot table is
-// cleared, as in the element pass.
+// plan checked it).
 template <int S>
 struct RoundTable {
     int32_t key[S];
@@ -158,33 +157,41 @@ k_mesh_tiled_rounds(MeshView m, MeshPass p, TiledView tv) {
     const bool ok = e < m.n_elems;
     const double fb = p.fbar ? p.fbar[0] : 1.0;
     const uint32_t shift = tv.round_shift;
+    // Lanes past the last element read its rows (no tile starts past it) and
+    // add nothing: the loads and the gather need no branch, so the gather is
+    // issued once conn has arrived.  The slot table is cleared while the
+    // gather is in flight.  Only the adjoint (no objective) can be handed
+    // stored forward values.
+    const int64_t ec = ok ? e : m.n_elems - 1;
     int32_t cr[K];
     T br[K];
-    double wd = 0.0, u = 0.0;
-    if (ok) {
-        load_conn_row<T, K>(m.conn, e, cr);
-        load_b_row<K>(B, e, br);
-        wd = to_f64(W[e]);
-    }
-    for (int q = threadIdx.x; q < S; q += blockDim.x) {
-        tab.key[q] = -1;
-        tab.val[q] = 0.0;
-    }
-    if (ok) {
-        if (p.u_in) {
-            u = p.u_in[e];
-        } else {
-            T xv[K];
-#pragma unroll
-            for (int j = 0; j < K; ++j) xv[j] = X[cr[j]];
-#pragma unroll
-            for (int j = 0; j < K; ++j) u += to_f64(br[j]) * to_f64(xv[j]);
+    load_conn_row<T, K>(m.conn, ec, cr);
+    load_b_row<K>(B, ec, br);
+    const double wd = to_f64(W[ec]);
+    double u = 0.0;
+    bool stored = false;
+    if constexpr (!OBJ) stored = p.u_in != nullptr;
+    if (stored) {
+        u = p.u_in[ec];
+        for (int q = threadIdx.x; q < S; q += blockDim.x) {
+            tab.key[q] = -1;
+            tab.val[q] = 0.0;
         }
+    } else {
+        T xv[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) xv[j] = X[cr[j]];
+        for (int q = threadIdx.x; q < S; q += blockDim.x) {
+            tab.key[q] = -1;
+            tab.val[q] = 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) u += to_f64(br[j]) * to_f64(xv[j]);
     }
     const double s2 = u * u;
     double tsum = 0.0;
-    if constexpr (OBJ) tsum = wd * psi_from_sq(s2);
-    const double v = fb * wd * dpsi_from(u, s2);
+    if constexpr (OBJ) tsum = ok ? wd * psi_from_sq(s2) : 0.0;
+    const double v = ok ? fb * wd * dpsi_from(u, s2) : 0.0;
     __syncthreads();  // the table is clear
 #pragma unroll
     for (int j = 0; j < K; ++j) {
