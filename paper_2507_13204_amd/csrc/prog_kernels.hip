@@ -297,19 +297,24 @@ __global__ void __launch_bounds__(BS) k_group(GroupDev g) {
     // needs the gather rows but no forward values.
     const bool values = FWD || g.n_ops > 0;
     if (ok) {
-        // Every load first: the gather row, the leaves, then the gathered entries.
+        // Every load first: the gather row, the gathered entries (issued as
+        // soon as the row's connectivity is in: the leaves' loads sit behind
+        // branches, and issued before the gather they made the gather wait
+        // for B as well), then the leaves.
+        double xv[K > 0 ? K : 1];
         if constexpr (K > 0) {
             load_conn_row<double, K>(g.gconn, i, row.c);
             load_b_row<K>(g.gB, i, row.b);
+            if (values) {
+#pragma unroll
+                for (int j = 0; j < K; ++j) xv[j] = g.gsrc[row.c[j]];
+            }
         }
 #pragma unroll
         for (int l = 0; l < NL; ++l)
             if (l < L && l != g.gather_slot) r.r[l] = g.leaf[l][i];
         if (!values) {
         } else if constexpr (K > 0) {
-            double xv[K];
-#pragma unroll
-            for (int j = 0; j < K; ++j) xv[j] = g.gsrc[row.c[j]];
             double u = 0.0;
 #pragma unroll
             for (int j = 0; j < K; ++j) u += row.b[j] * xv[j];
