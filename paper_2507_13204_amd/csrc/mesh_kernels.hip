@@ -36,8 +36,11 @@ k_mesh_elem(MeshView m, MeshPass p) {
                p.hash_shift};
     AggOf<AGG>* tab = nullptr;
     if constexpr (AGG > 0) tab = &agg;
-    const double tsum = elem_tile<T, K, MODE, EPT, AGG>(a, (int64_t)lb * blockDim.x * EPT, n_items,
-                                                        0, fb, tab);
+    // LDS table clear before the gather for FP64 rows, after it for FP32
+    // rows (measured: 0.5 us and 0.7 us faster respectively on 128^3).
+    constexpr bool clear_early = !std::is_same<T, float>::value;
+    const double tsum = elem_tile<T, K, MODE, EPT, AGG, clear_early>(
+        a, (int64_t)lb * blockDim.x * EPT, n_items, 0, fb, tab);
     if constexpr (has_sum(MODE)) {
         const double s = block_sum_dyn(tsum, lds);
         if (threadIdx.x == 0) p.partials[p.partial_base + lb] = s;
