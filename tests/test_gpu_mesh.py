@@ -297,6 +297,32 @@ def test_non_finite_values_propagate_to_the_touched_nodes_only(adj, onepass, bad
     _check(m, f2.item(), g2.cpu().numpy())
 
 
+@pytest.mark.parametrize("adj,onepass", [("atomic", True), ("atomic", False), ("gather", True),
+                                         ("colour", True), ("tiled", True)])
+def test_overflow_in_the_last_element_gives_plus_inf(adj, onepass):
+    """A huge x at the last node makes the last element's term w psi(u)
+    overflow to +Inf.  Every term is >= 0, so f is +Inf exactly, not NaN: the
+    lanes past the last element of the ragged final workgroup, which read
+    that element's rows again, must add nothing (not 0 * Inf).  The gradient
+    is finite everywhere (psi' grows linearly) and matches the oracle away
+    from the last element's nodes."""
+    m = inputs.hex_mesh(23, seed=6)          # 22^3 = 10,648 elements: a ragged last workgroup
+    xh = m.x.copy()
+    xh[m.n_nodes - 1] = 1e200
+    mm = inputs.Mesh(m.n_nodes, m.n_elems, m.k, m.conn, m.B, m.w, xh, m.name)
+    obj, x = _obj(mm, "f64", adjoint=adj, onepass=onepass)
+    f, g = obj.gradient(x)
+    assert f.item() == float("inf")
+    with np.errstate(all="ignore"):
+        _, g_ref = _oracle_grad(mm)
+    gh = g.cpu().numpy()
+    assert np.all(np.isfinite(gh))
+    touched = np.unique(m.conn[np.any(m.conn == m.n_nodes - 1, axis=1)])
+    other = np.setdiff1d(np.arange(m.n_nodes), touched)
+    assert rel(gh[other], g_ref[other]) <= TOL_F64_G
+    assert rel(gh[touched] * 1e-190, g_ref[touched] * 1e-190) <= TOL_F64_G
+
+
 @pytest.mark.parametrize("name", ["hex23", "rand_k8", "rand_k4", "chain10k"])
 @pytest.mark.parametrize("scatter", [0, 1, 2, 3])
 @pytest.mark.parametrize("block,tile", [(256, 1), (128, 2), (64, 4), (512, 1)])
