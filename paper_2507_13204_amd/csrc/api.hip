@@ -163,6 +163,8 @@ struct pg_plan_s {
     // colour classes: elements of colour c are elist[colour_off[c] .. colour_off[c+1])
     std::vector<int64_t> colour_off;
     size_t o_elist = NONE;
+    // colour-major copies of conn, B and w (rows class by class)
+    size_t o_pconn = NONE, o_pB = NONE, o_pw = NONE;
     // batch
     BatchView batch;
     std::vector<pg_instance> inst;
@@ -345,6 +347,12 @@ void layout_mesh(pg_plan_s* p) {
         p->n_partials = (size_t)std::max<int64_t>(p->mesh_blocks_n, 1) + kMaxColours;
         p->o_partials = L.take(sizeof(double) * p->n_partials);
         p->o_elist = L.take(sizeof(int32_t) * (size_t)m.n_elems);
+        // Colour-major copies of the rows: a class's elements lie every other
+        // element in the numbering, so reading them in place fetches lines
+        // shared with the other classes; the copies are read contiguously.
+        p->o_pconn = L.take(sizeof(int32_t) * (size_t)(m.n_elems * m.k));
+        p->o_pB = L.take(esize(p->dtype) * (size_t)(m.n_elems * m.k));
+        p->o_pw = L.take(esize(p->dtype) * (size_t)m.n_elems);
     }
     // FP32 gradients accumulate in an FP64 buffer before rounding once.
     if (p->dtype == PG_F32) p->o_gacc = L.take(sizeof(double) * (size_t)m.n_nodes);
@@ -644,15 +652,31 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
         q.gacc = f32 ? p->at<double>(p->o_gacc) : static_cast<double*>(grad);
         if (!f32 && !acc) PG_HIP(launch_zero(q.gacc, sizeof(double) * (size_t)m.n_nodes, s));
         const int32_t* elist = p->at<int32_t>(p->o_elist);
+        // The passes read the colour-major row copies, except when stored
+        // forward values (indexed by element) are read or written.
+        const bool copies = !q.u_in && !q.u_store;
+        const size_t esz = esize(p->dtype);
         int64_t slot = 0;
         PG_HIP(tmark(p, 1, true, s));
         for (size_t c = 0; c + 1 < p->colour_off.size(); ++c) {
-            q.elist = elist + p->colour_off[c];
-            q.elist_n = p->colour_off[c + 1] - p->colour_off[c];
+            const int64_t off = p->colour_off[c], cnt = p->colour_off[c + 1] - off;
             q.partial_base = slot;
-            if (q.elist_n == 0) continue;
-            PG_HIP(launch_mesh_elem(m, obj ? M_GRAD_COLOUR : M_ADJ_COLOUR, q, s));
-            slot += mesh_blocks(q.elist_n, q.block, k_in_registers(m.k) ? q.ept : 1);
+            if (cnt == 0) continue;
+            if (copies) {
+                MeshView mc = m;
+                mc.n_elems = cnt;
+                mc.conn = p->at<int32_t>(p->o_pconn) + off * m.k;
+                mc.B = p->at<char>(p->o_pB) + (size_t)(off * m.k) * esz;
+                mc.w = p->at<char>(p->o_pw) + (size_t)off * esz;
+                q.elist = nullptr;
+                q.elist_n = 0;
+                PG_HIP(launch_mesh_elem(mc, obj ? M_GRAD_COLOUR : M_ADJ_COLOUR, q, s));
+            } else {
+                q.elist = elist + off;
+                q.elist_n = cnt;
+                PG_HIP(launch_mesh_elem(m, obj ? M_GRAD_COLOUR : M_ADJ_COLOUR, q, s));
+            }
+            slot += mesh_blocks(cnt, q.block, k_in_registers(m.k) ? q.ept : 1);
         }
         PG_HIP(tmark(p, 1, false, s));
         if (f32 && obj && f_out)  // the conversion's first workgroup also sums f
@@ -1034,6 +1058,9 @@ pg_status mesh_bind(pg_plan p, hipStream_t s) {
     if (p->opt.adjoint == PG_ADJ_COLOUR) {
         pg_status cst = mesh_colour(p, s);
         if (cst != PG_OK) return cst;
+        PG_HIP(launch_permute_rows(p->at<int32_t>(p->o_elist), m.n_elems, m.k, m.conn, m.B, m.w,
+                                   m.dtype == F64, p->at<int32_t>(p->o_pconn),
+                                   p->at<char>(p->o_pB), p->at<char>(p->o_pw), s));
     }
     if (p->opt.adjoint == PG_ADJ_TILED) {
         pg_status tst = mesh_tiled_build(p, s);

@@ -177,6 +177,10 @@ hipError_t launch_segmented_sum(const double* partials, const int64_t* seg, int6
                                 double* out, hipStream_t s);
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// conn, B and w rows gathered into the order of `list` (n rows of k entries).
+hipError_t launch_permute_rows(const int32_t* list, int64_t n, int32_t k, const int32_t* conn,
+                               const void* B, const void* w, bool f64, int32_t* pconn, void* pB,
+                               void* pw, hipStream_t s);
 
 // dst (FP32) (=|+=) src (FP64); clear: src is zeroed as it is read.
 hipError_t launch_f64_to_f32(double* src, float* dst, int64_t n, int accumulate, int clear,

@@ -342,4 +342,39 @@ hipError_t launch_csr_fill_sort(const int32_t* conn, int64_t n_items, int64_t n_
     return hipGetLastError();
 }
 
+// Rows of conn, B and w copied into the order of a list of elements (the
+// colour classes, class by class): out row r is element list[r].  One thread
+// per (row, entry).
+template <typename T>
+__global__ void k_permute_rows(const int32_t* __restrict__ list, int64_t n, int32_t k,
+                               const int32_t* __restrict__ conn, const T* __restrict__ B,
+                               const T* __restrict__ w, int32_t* __restrict__ pconn,
+                               T* __restrict__ pB, T* __restrict__ pw) {
+    const int64_t items = n * k;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < items;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = q / k, j = q - r * k;
+        const int64_t e = list[r];
+        pconn[q] = conn[e * k + j];
+        pB[q] = B[e * k + j];
+        if (j == 0) pw[r] = w[e];
+    }
+}
+
+hipError_t launch_permute_rows(const int32_t* list, int64_t n, int32_t k, const int32_t* conn,
+                               const void* B, const void* w, bool f64, int32_t* pconn, void* pB,
+                               void* pw, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const unsigned grid = stream_grid(n * k, 256, 1 << 16);
+    if (f64)
+        hipLaunchKernelGGL(k_permute_rows<double>, dim3(grid), dim3(256), 0, s, list, n, k, conn,
+                           static_cast<const double*>(B), static_cast<const double*>(w), pconn,
+                           static_cast<double*>(pB), static_cast<double*>(pw));
+    else
+        hipLaunchKernelGGL(k_permute_rows<float>, dim3(grid), dim3(256), 0, s, list, n, k, conn,
+                           static_cast<const float*>(B), static_cast<const float*>(w), pconn,
+                           static_cast<float*>(pB), static_cast<float*>(pw));
+    return hipGetLastError();
+}
+
 }  // namespace pg
