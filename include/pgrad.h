@@ -78,7 +78,11 @@ typedef enum {
     PG_ADJ_GATHER = 2, /* deterministic: node-parallel gather over the
                           transposed (node -> element) connectivity */
     PG_ADJ_COLOUR = 3, /* deterministic: element colour classes, one
-                          non-atomic pass per colour */
+                          non-atomic pass per colour; the bind copies conn,
+                          B and w into colour-major order in the workspace
+                          (per element k * 4 + (k + 1) * element-size bytes
+                          more), which the passes read unless a stored tape
+                          is in use */
     PG_ADJ_TILED = 4   /* deterministic: each workgroup sums its tile's
                           contributions per node in LDS in a fixed order
                           (local incidence lists built at bind), then a
