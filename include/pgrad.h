@@ -76,7 +76,10 @@ typedef enum {
     PG_ADJ_AUTO = 0,   /* library choice (currently PG_ADJ_ATOMIC) */
     PG_ADJ_ATOMIC = 1, /* element-parallel scatter with FP64 atomic adds */
     PG_ADJ_GATHER = 2, /* deterministic: node-parallel gather over the
-                          transposed (node -> element) connectivity */
+                          transposed (node -> element) connectivity, built
+                          at bind with B's coefficients copied into its
+                          order (per incidence 4 + element-size bytes of
+                          workspace, besides the offsets) */
     PG_ADJ_COLOUR = 3, /* deterministic: element colour classes, one
                           non-atomic pass per colour; the bind copies conn,
                           B and w into colour-major order in the workspace

@@ -183,7 +183,7 @@ struct pg_plan_s {
     // workspace
     size_t ws_bytes = 0;
     size_t o_partials = NONE, o_flag = NONE, o_u = NONE, o_v = NONE, o_offs = NONE,
-           o_cursor = NONE, o_inc = NONE, o_scan = NONE, o_gacc = NONE, o_colpart = NONE,
+           o_cursor = NONE, o_inc = NONE, o_binc = NONE, o_scan = NONE, o_gacc = NONE, o_colpart = NONE,
            o_tiles = NONE, o_vmat = NONE, o_tbase = NONE, o_loff = NONE, o_lidx = NONE,
            o_stage = NONE, o_noff = NONE, o_npos = NONE, o_small = NONE, o_ticket = NONE,
            o_small_meta = NONE;
@@ -322,6 +322,8 @@ void layout_mesh(pg_plan_s* p) {
         p->o_offs = L.take(sizeof(int32_t) * (size_t)(m.n_nodes + 1));
         p->o_cursor = L.take(sizeof(int32_t) * (size_t)m.n_nodes);
         p->o_inc = L.take(sizeof(int32_t) * (size_t)(m.n_elems * m.k));
+        // B's coefficients in incidence order (read as a stream by the node pass)
+        p->o_binc = L.take(esize(p->dtype) * (size_t)(m.n_elems * m.k));
         p->o_scan = L.take(sizeof(int64_t) * (size_t)scan_scratch_items(m.n_nodes));
     }
     if (p->opt.adjoint == PG_ADJ_TILED) {
@@ -703,7 +705,7 @@ pg_status mesh_run(pg_plan p, const void* x, const double* fbar, void* grad, dou
         PG_HIP(tmark(p, 1, true, s));
         PG_HIP(launch_mesh_elem(m, obj ? M_GRAD_V : M_ADJ_V, q, s));
         PG_HIP(launch_mesh_node_gather(m, p->at<int32_t>(p->o_offs), p->at<int32_t>(p->o_inc),
-                                       q.v_out, grad, acc, 256, s));
+                                       p->at<char>(p->o_binc), q.v_out, grad, acc, 256, s));
         PG_HIP(tmark(p, 1, false, s));
     } else {  // atomic
         if (f32) {
@@ -1072,6 +1074,8 @@ pg_status mesh_bind(pg_plan p, hipStream_t s) {
                                      p->at<int64_t>(p->o_scan), s));
         PG_HIP(launch_csr_fill_sort(m.conn, items, m.n_nodes, offs, p->at<int32_t>(p->o_cursor),
                                     p->at<int32_t>(p->o_inc), s));
+        PG_HIP(launch_gather_entries(p->at<int32_t>(p->o_inc), items, m.B, m.dtype == F64,
+                                     p->at<char>(p->o_binc), s));
         PG_HIP(hipStreamSynchronize(s));
     }
     return PG_OK;

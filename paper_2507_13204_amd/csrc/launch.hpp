@@ -166,8 +166,8 @@ hipError_t launch_mesh_elem(const MeshView& m, MeshMode mode, const MeshPass& p,
 // Node-parallel gather of the reverse pass over the transposed connectivity:
 // g[n] (+)= sum_{p in offs[n]..offs[n+1]} v[inc[p]/k] * B[inc[p]].
 hipError_t launch_mesh_node_gather(const MeshView& m, const int32_t* offs, const int32_t* inc,
-                                   const double* v, void* grad, int accumulate, int block,
-                                   hipStream_t s);
+                                   const void* binc, const double* v, void* grad, int accumulate,
+                                   int block, hipStream_t s);
 
 // out[0] (=|+=) sum of partials[0..n) in a fixed order (one workgroup).
 hipError_t launch_final_sum(const double* partials, int64_t n, double* out, hipStream_t s);
@@ -177,6 +177,9 @@ hipError_t launch_segmented_sum(const double* partials, const int64_t* seg, int6
                                 double* out, hipStream_t s);
 
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// out[q] = B[idx[q]] for q < n (B's coefficients in incidence order).
+hipError_t launch_gather_entries(const int32_t* idx, int64_t n, const void* B, bool f64, void* out,
+                                 hipStream_t s);
 // conn, B and w rows gathered into the order of `list` (n rows of k entries).
 hipError_t launch_permute_rows(const int32_t* list, int64_t n, int32_t k, const int32_t* conn,
                                const void* B, const void* w, bool f64, int32_t* pconn, void* pB,

@@ -102,20 +102,37 @@ k_mesh_elem_dyn(MeshView m, MeshPass p) {
     }
 }
 
+// Node-parallel sum over the transposed connectivity: node n adds
+// v_e * B[e, j] over its incidences in ascending (e, j) order.  B's
+// coefficients are read in incidence order from `binc` (copied at bind), so
+// they stream; the incidences are taken four at a time so that their loads
+// are in flight together, the additions staying in order.
 template <typename T, int K>
 __global__ void __launch_bounds__(1024)
 k_mesh_node_gather(int64_t n_nodes, int32_t k, const int32_t* __restrict__ offs,
                    const int32_t* __restrict__ inc, const double* __restrict__ v,
-                   const T* __restrict__ B, T* __restrict__ grad, int accumulate) {
+                   const T* __restrict__ binc, T* __restrict__ grad, int accumulate) {
     const uint32_t lb = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t n = (int64_t)lb * blockDim.x + threadIdx.x;
     if (n >= n_nodes) return;
     const int32_t p0 = offs[n], p1 = offs[n + 1];
     double acc = 0.0;
-    for (int32_t q = p0; q < p1; ++q) {
-        const int32_t idx = inc[q];
-        const int32_t e = K > 0 ? idx / K : idx / k;
-        acc += v[e] * to_f64(B[idx]);
+    for (int32_t q = p0; q < p1; q += 4) {
+        int32_t e[4];
+        double b[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const bool in = q + r < p1;
+            const int32_t idx = in ? inc[q + r] : 0;
+            e[r] = in ? (K > 0 ? idx / K : idx / k) : -1;
+            b[r] = in ? to_f64(binc[q + r]) : 0.0;
+        }
+        double ve[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ve[r] = e[r] >= 0 ? v[e[r]] : 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (e[r] >= 0) acc += ve[r] * b[r];
     }
     if (accumulate)
         grad[n] = static_cast<T>(to_f64(grad[n]) + acc);
@@ -212,27 +229,27 @@ hipError_t launch_mesh_elem(const MeshView& m, MeshMode mode, const MeshPass& p,
 }
 
 hipError_t launch_mesh_node_gather(const MeshView& m, const int32_t* offs, const int32_t* inc,
-                                   const double* v, void* grad, int accumulate, int block,
-                                   hipStream_t s) {
+                                   const void* binc, const double* v, void* grad, int accumulate,
+                                   int block, hipStream_t s) {
     if (m.n_nodes == 0) return hipSuccess;
     const unsigned nb = (unsigned)((m.n_nodes + block - 1) / block);
     if (m.dtype == F64) {
         if (m.k == 8)
             hipLaunchKernelGGL((k_mesh_node_gather<double, 8>), dim3(nb), dim3(block), 0, s,
-                               m.n_nodes, m.k, offs, inc, v, (const double*)m.B, (double*)grad,
+                               m.n_nodes, m.k, offs, inc, v, (const double*)binc, (double*)grad,
                                accumulate);
         else
             hipLaunchKernelGGL((k_mesh_node_gather<double, 0>), dim3(nb), dim3(block), 0, s,
-                               m.n_nodes, m.k, offs, inc, v, (const double*)m.B, (double*)grad,
+                               m.n_nodes, m.k, offs, inc, v, (const double*)binc, (double*)grad,
                                accumulate);
     } else {
         if (m.k == 8)
             hipLaunchKernelGGL((k_mesh_node_gather<float, 8>), dim3(nb), dim3(block), 0, s,
-                               m.n_nodes, m.k, offs, inc, v, (const float*)m.B, (float*)grad,
+                               m.n_nodes, m.k, offs, inc, v, (const float*)binc, (float*)grad,
                                accumulate);
         else
             hipLaunchKernelGGL((k_mesh_node_gather<float, 0>), dim3(nb), dim3(block), 0, s,
-                               m.n_nodes, m.k, offs, inc, v, (const float*)m.B, (float*)grad,
+                               m.n_nodes, m.k, offs, inc, v, (const float*)binc, (float*)grad,
                                accumulate);
     }
     return hipGetLastError();

@@ -377,4 +377,27 @@ hipError_t launch_permute_rows(const int32_t* list, int64_t n, int32_t k, const 
     return hipGetLastError();
 }
 
+// out[q] = B[idx[q]]: the coefficients of B in the order of a list of
+// incidences (the transposed connectivity, node by node).
+template <typename T>
+__global__ void k_gather_entries(const int32_t* __restrict__ idx, int64_t n, const T* __restrict__ B,
+                                 T* __restrict__ out) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        out[q] = B[idx[q]];
+}
+
+hipError_t launch_gather_entries(const int32_t* idx, int64_t n, const void* B, bool f64, void* out,
+                                 hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const unsigned grid = stream_grid(n, 256, 1 << 16);
+    if (f64)
+        hipLaunchKernelGGL(k_gather_entries<double>, dim3(grid), dim3(256), 0, s, idx, n,
+                           static_cast<const double*>(B), static_cast<double*>(out));
+    else
+        hipLaunchKernelGGL(k_gather_entries<float>, dim3(grid), dim3(256), 0, s, idx, n,
+                           static_cast<const float*>(B), static_cast<float*>(out));
+    return hipGetLastError();
+}
+
 }  // namespace pg
