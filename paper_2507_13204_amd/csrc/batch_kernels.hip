@@ -48,8 +48,10 @@ k_batch_tiles(BatchView bv, BatchPass p) {
     const int64_t inst = cur.slot_inst >> 40;
     double fb = 1.0;
     if constexpr (has_rev(MODE)) fb = p.fbar ? p.fbar[inst] : 1.0;
+    // 64-bit gather addresses: the 32-bit buffer offsets that help the
+    // single mesh measured 0.8% slower here
     TileArgs a{bv.conn, bv.B, bv.w, p.x, nullptr, p.u_in, p.u_store, nullptr,
-               static_cast<double*>(p.grad), nullptr, (uint32_t)(cur.shift_noff >> 40)};
+               static_cast<double*>(p.grad), nullptr, (uint32_t)(cur.shift_noff >> 40), 0u};
     const double tsum = elem_tile<T, K, MODE, EPT, AGG, false>(a, cur.first, cur.end,
                                                                cur.shift_noff & kNoffMask, fb, tab);
     if constexpr (has_obj(MODE)) {

@@ -33,7 +33,7 @@ k_mesh_elem(MeshView m, MeshPass p) {
     double fb = 1.0;
     if constexpr (has_rev(MODE)) fb = p.fbar ? p.fbar[0] : 1.0;
     TileArgs a{m.conn, m.B, m.w, p.x, p.xd, p.u_in, p.u_store, p.v_out, p.gacc, p.elist,
-               p.hash_shift};
+               p.hash_shift, buffer_bytes<T>(m.n_nodes)};
     AggOf<AGG>* tab = nullptr;
     if constexpr (AGG > 0) tab = &agg;
     // LDS table clear before the gather for FP64 rows, after it for FP32
