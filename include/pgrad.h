@@ -130,7 +130,9 @@ typedef struct {
                            workgroup's contributions per node in an LDS hash
                            table, then one global atomic per node; a single
                            mesh's plan picks a 2048- or 4096-slot table by
-                           simulating it on sampled workgroups), 1 = one
+                           simulating it on sampled workgroups, and keeps
+                           2048 only if a check of every workgroup at bind
+                           finds no two nodes on one home slot), 1 = one
                            global atomic per contribution, 2 = combine in a
                            4096-slot table, 3 = combine in a 2048-slot table
                            (2 and 3: single meshes; batches treat them as 0) */

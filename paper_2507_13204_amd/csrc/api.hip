@@ -1045,6 +1045,21 @@ pg_status mesh_bind(pg_plan p, hipStream_t s) {
                                           (int64_t)p->opt.block * p->opt.tile, kHashSamples, tiles, s);
         if (hst != PG_OK) return hst;
         table_of(tiles, &p->agg_slots, &p->hash_shift);
+        // The 2048-slot table is kept only if no workgroup of the pass finds
+        // two of its nodes on one home slot: the sample can miss the few
+        // workgroups where the hash puts two node runs in one window, and
+        // their probe chains cost far more than the smaller table saves.
+        if (p->opt.scatter == 0 && p->agg_slots == 2048) {
+            PG_HIP(launch_table_check(m.conn, m.n_elems, m.k, (int64_t)p->opt.block * p->opt.tile,
+                                      p->hash_shift, 2048, flag + 1, s));
+            int32_t miss = 0;
+            PG_HIP(hipMemcpyAsync(&miss, flag + 1, sizeof miss, hipMemcpyDeviceToHost, s));
+            PG_HIP(hipStreamSynchronize(s));
+            if (miss) {
+                p->agg_slots = 4096;
+                p->hash_shift = shift_of(tiles);
+            }
+        }
         if (p->opt.scatter >= 2) {  // the caller fixed the table size
             p->agg_slots = p->opt.scatter == 2 ? 4096 : 2048;
             std::vector<const int32_t*> ptr;

@@ -202,6 +202,13 @@ hipError_t launch_scale(Dtype dt, int64_t n, const double* alpha, const void* x,
 // flag |= 1 if any conn entry is outside [0, n_nodes); cnt[node] += 1 when cnt.
 hipError_t launch_validate_count(const int32_t* conn, int64_t n_items, int64_t n_nodes,
                                  int32_t* cnt, int32_t* flag, hipStream_t s);
+// For an element pass whose workgroup w takes elements [w * span, (w + 1) *
+// span) (k node numbers each): *miss += the number of inserts, over all
+// workgroups, that find another node in their home slot of an S-slot LDS
+// table with hash rotation `shift` (S = 2048 or 4096).  Zero means no
+// workgroup of the pass probes.
+hipError_t launch_table_check(const int32_t* conn, int64_t n_elems, int32_t k, int64_t span,
+                              uint32_t shift, int slots, int32_t* miss, hipStream_t s);
 // Exclusive scan: out[0..n] with out[n] = total.  scratch holds
 // scan_scratch_items(n) int64 values.
 int64_t scan_scratch_items(int64_t n);

@@ -690,8 +690,20 @@ pg_status pg_prog_bind_workspace(pg_prog p, void* ws, size_t bytes) {
             ptr.push_back(t.data());
             cnt.push_back((int64_t)t.size());
         }
-        if (!tiles.empty())
-            choose_table(ptr.data(), cnt.data(), (int64_t)tiles.size(), &g.agg_slots, &g.hash_shift);
+        if (tiles.empty()) continue;
+        choose_table(ptr.data(), cnt.data(), (int64_t)tiles.size(), &g.agg_slots, &g.hash_shift);
+        // The smaller table only if no workgroup of the gather would probe in it.
+        if (g.agg_slots == 2048) {
+            PG_HIP(launch_zero(flag + 2, sizeof(int32_t), nullptr));
+            PG_HIP(launch_table_check(op.conn, op.n, op.k, span, g.hash_shift, 2048, flag + 2, nullptr));
+            int32_t miss = 0;
+            PG_HIP(hipMemcpy(&miss, flag + 2, sizeof miss, hipMemcpyDeviceToHost));
+            if (miss) {
+                g.agg_slots = 4096;
+                g.hash_shift = choose_hash_shift(ptr.data(), cnt.data(), (int64_t)tiles.size(), 4096,
+                                                 nullptr);
+            }
+        }
     }
     p->ws = static_cast<char*>(ws);
     return PG_OK;

@@ -120,6 +120,28 @@ k_validate_count(const int32_t* __restrict__ conn, int64_t n_items, int64_t n_no
     if (bad) atomicOr(flag, 1);
 }
 
+// One workgroup per element-pass workgroup: its node numbers are put in
+// their home slots of an S-slot table; an insert that finds another node
+// there is counted (any two distinct nodes of a workgroup that share a home
+// slot give at least one such insert, whatever the order).
+template <int S>
+__global__ void __launch_bounds__(256)
+k_table_check(const int32_t* __restrict__ conn, int64_t n_elems, int32_t k, int64_t span,
+              uint32_t shift, int32_t* __restrict__ miss) {
+    __shared__ int32_t key[S];
+    for (int q = threadIdx.x; q < S; q += blockDim.x) key[q] = -1;
+    __syncthreads();
+    const int64_t e0 = (int64_t)blockIdx.x * span;
+    const int64_t e1 = e0 + span < n_elems ? e0 + span : n_elems;
+    int m = 0;
+    for (int64_t q = e0 * k + threadIdx.x; q < e1 * k; q += blockDim.x) {
+        const int32_t nd = conn[q];
+        const int32_t old = atomicCAS(&key[agg_slot((uint32_t)nd, shift, (uint32_t)S)], -1, nd);
+        m += (old != -1 && old != nd) ? 1 : 0;
+    }
+    if (m) atomicAdd(miss, m);
+}
+
 // Exclusive scan in three launches: per-chunk totals, a scan of the totals
 // by one workgroup, then per-chunk local scans offset by the chunk prefix.
 constexpr int kScanBS = 256;
@@ -305,6 +327,22 @@ hipError_t launch_validate_count(const int32_t* conn, int64_t n_items, int64_t n
     if (n_items == 0) return hipSuccess;
     hipLaunchKernelGGL(k_validate_count, dim3(stream_grid(n_items, 256 * 8, 8192)), dim3(256), 0,
                        s, conn, n_items, n_nodes, cnt, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_table_check(const int32_t* conn, int64_t n_elems, int32_t k, int64_t span,
+                              uint32_t shift, int slots, int32_t* miss, hipStream_t s) {
+    if (n_elems == 0 || span <= 0) return hipSuccess;
+    const int64_t nw = (n_elems + span - 1) / span;
+    if (nw > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (slots == 2048)
+        hipLaunchKernelGGL(k_table_check<2048>, dim3((unsigned)nw), dim3(256), 0, s, conn, n_elems,
+                           k, span, shift, miss);
+    else if (slots == 4096)
+        hipLaunchKernelGGL(k_table_check<4096>, dim3((unsigned)nw), dim3(256), 0, s, conn, n_elems,
+                           k, span, shift, miss);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

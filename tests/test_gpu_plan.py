@@ -73,3 +73,40 @@ def test_structures_absent_from_other_plans_are_refused():
         assert ei.value.code == EUNSUPPORTED
     info = atomic.info()
     assert info["bound"] == 1 and info["lds_slots"] in (2048, 4096) and info["adjoint"] == 1
+
+
+def _tile_order(m1, tx, ty, tz):
+    """Element numbers of an m1^3 hex grid taken tile by tile (tiles of
+    tx x ty x tz elements; lexicographic inside a tile and across tiles)."""
+    kk, jj, ii = np.meshgrid(np.arange(m1), np.arange(m1), np.arange(m1), indexing="ij")
+    ii, jj, kk = ii.ravel(), jj.ravel(), kk.ravel()
+    ntx, nty = -(-m1 // tx), -(-m1 // ty)
+    tile = (ii // tx) + ntx * ((jj // ty) + nty * (kk // tz))
+    local = (ii % tx) + tx * ((jj % ty) + ty * (kk % tz))
+    return np.lexsort((local, tile))
+
+
+def test_smaller_lds_table_needs_every_workgroup_collision_free():
+    """The plan picks the LDS table of the combined scatter on 64 sampled
+    workgroups, and keeps the 2048-slot table only if no workgroup of the
+    whole pass has two nodes on one home slot.  The 128^3 mesh with its
+    elements renumbered in tiles of whole rows x 2 x 2: the sampled
+    workgroups have no collision at 2048 slots, about 3% of all workgroups
+    have some, so the plan must take 4096 slots; the lexicographic order has
+    none anywhere and keeps 2048.  Both give the oracle's gradient."""
+    from _helpers import TOL_F64_F, TOL_F64_G, rel, srel
+    from paper_2507_13204_amd import MeshObjective
+    m = inputs.hex_mesh(128)
+    p = _tile_order(127, 128, 2, 2)
+    assert np.array_equal(np.sort(p), np.arange(m.n_elems))
+    lex = _plan(m, "atomic")
+    tiled = MeshObjective(to_dev(m.conn[p]), to_dev(m.B[p]), to_dev(m.w[p]), m.n_nodes)
+    assert lex.info()["lds_slots"] == 2048
+    assert tiled.info()["lds_slots"] == 4096
+    f_r, g_r = oracle.mesh_gradient(m.n_nodes, m.conn, m.B, m.w, m.x)
+    x = to_dev(m.x)
+    for obj in (lex, tiled):
+        f, g = obj.gradient(x)
+        torch.cuda.synchronize()
+        assert srel(float(f), f_r) <= TOL_F64_F
+        assert rel(g.cpu().numpy(), g_r) <= TOL_F64_G
